@@ -1,0 +1,6 @@
+"""Seeded synthetic inputs (design matrices and probit outcomes)."""
+from .datasets import (Dataset, probit_design, sparse_beta, leading_beta, config1, config2,
+                       config3, eq13, batch_shapes, batch_dataset, bf16_bits, bf16_to_f32)
+
+__all__ = ["Dataset", "probit_design", "sparse_beta", "leading_beta", "config1", "config2",
+           "config3", "eq13", "batch_shapes", "batch_dataset", "bf16_bits", "bf16_to_f32"]
