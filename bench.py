@@ -1,0 +1,151 @@
+"""Benchmark: Gibbs sweeps per second of the Horseshoe Probit sampler on one
+MI355X, at N = 1,000,000 rows and p = 1000 predictors (X float32, 4 GB).
+
+One step = one full Gibbs sweep (z | beta over all rows fused with X^T z;
+lambda, tau; the float64 Cholesky draw of beta; nu, xi; the draw record).
+Inputs are seeded synthetic data (the paper's Section 6.1 design with an
+intercept and 10 nonzero coefficients) resident in HBM before timing starts.
+
+Prints one JSON line.  Also reports:
+  roofline      the z pass (the dominant kernel): algorithmic bytes per launch
+                (N p 4 + N) over its mean duration from HIP events on the
+                library's stream, against the 8 TB/s HBM peak
+  cpu_baseline  the float64 oracle timed on this host on a bounded sample of
+                the same workload (whole sweeps, one thread)
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gibbs sweeps/sec and HBM GB/s at N=1e6,p=1000; chain-sweeps/sec batched vs plain"
+HBM_PEAK_GBPS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--N", type=int, default=1_000_000)
+    ap.add_argument("--p", type=int, default=1000)
+    ap.add_argument("--x-type", default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "zpass_traffic.json"))
+    return ap.parse_args()
+
+
+def cpu_baseline(d, seconds):
+    """Whole oracle sweeps on the same data until `seconds` have elapsed."""
+    import numpy as np
+    from oracle import oracle as orc
+    # one-time Gram in float64 (untimed, like the GPU's creation step)
+    G = np.zeros((d.p, d.p))
+    step = 1 << 16
+    for r in range(0, d.N, step):
+        xb = d.X[r:r + step].astype(np.float64)
+        G += xb.T @ xb
+    ch = orc.Chain(d.p)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        ch.sweep_once(d.X, d.y, G, seed=1)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or n >= 50:
+            break
+    return {"value": n / el, "unit": "sweeps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} whole float64 oracle sweeps of the same N={d.N}, p={d.p} workload "
+                      f"from the cold start, single thread, {el:.1f} s; Gram formed beforehand "
+                      f"(untimed)"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the row-sharded design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1608_04329_amd import hsp
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    beta_true, idx = synth.sparse_beta(a.p, min(10, a.p - 1), 13)
+    d = synth.probit_design(a.N, a.p, beta_true, 13, True, f"n{a.N}_p{a.p}")
+    print(f"[bench] data N={a.N} p={a.p} generated in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    s = hsp.Sampler(d.X, d.y, seed=1, x_type=a.x_type, max_draws=max(64, a.steps + a.warmup))
+    print(f"[bench] sampler created (X copied, Gram formed) in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+
+    s.sweep(a.warmup)
+    s.sync()
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.sweep(a.steps)
+    s.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    zpass_ms, sweep_ms, n_timed = s.timing()
+    clamps, maxatt = s.counters()
+    s.set_timing(False)
+    print(f"[bench] {a.steps} sweeps in {elapsed:.3f}s; z pass {zpass_ms:.4f} ms, "
+          f"sweep {sweep_ms:.4f} ms (events)", file=sys.stderr, flush=True)
+
+    esz = 4 if a.x_type == "f32" else 2
+    zbytes = a.N * a.p * esz + a.N  # X once, y once
+    value = a.steps / elapsed
+    achieved = zbytes / (zpass_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(a.traffic_json):
+        try:
+            t = json.load(open(a.traffic_json))
+            if t.get("workload") == d.name and t.get("x_type") == a.x_type:
+                traffic = t.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "sweeps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(1e3 * elapsed / a.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if a.x_type == "f32" else "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"horseshoe_probit_gibbs_N{a.N}_p{a.p}_x{a.x_type}",
+                   "N": a.N, "p": a.p, "x_storage": a.x_type, "n_side_arith": "f32",
+                   "p_side_arith": "f64", "chains": 1},
+        "hbm_gbps": round(zbytes / (elapsed / a.steps) / 1e9, 1),
+        "zpass_ms": round(zpass_ms, 5),
+        "sweep_ms_events": round(sweep_ms, 5),
+        "max_tn_proposals": int(maxatt),
+        "lambda_clamps": int(clamps),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic},
+    }
+    s.close()
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(d, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,182 @@
+/*
+ * hsp.h -- C ABI of the MI355X (gfx950) Horseshoe Probit Gibbs sampler.
+ *
+ * The library runs the data-parallel Gibbs sweep of Terenin, Dong & Draper,
+ * "GPU-accelerated Gibbs sampling: a case study of the Horseshoe Probit
+ * model", Section 5, for the model of Eqs. (9)-(10):
+ *     y_i = 1{z_i > 0},  z_i ~ N(x_i beta, 1),
+ *     beta_j ~ N(0, lambda_j^2 tau^2),  lambda_j, tau ~ C+(0, 1),
+ * using the auxiliary-variable conditionals of Eq. (12).  One sweep is
+ *   (i)  z | beta (N truncated normals around X beta, Eq. 8 makes them
+ *        independent) in parallel with lambda^-2, followed by tau^-2;
+ *   (ii) beta | z, lambda, tau (X^T z and a Cholesky solve of
+ *        Q = X^T X + tau^-2 Lambda^-2, then a Gaussian draw), with nu^-1 and
+ *        xi^-1 alongside.
+ *
+ * All arithmetic runs in the library's HIP kernels.  N-sized work (X beta,
+ * the truncated-normal draws, X^T z) runs in float32 over X stored as
+ * float32 or bfloat16; everything p-sized (X^T X, Q, its Cholesky factor,
+ * the solves and the hyperparameters) runs in float64.
+ *
+ * Random numbers: Philox4x32-10 with key = seed and counter
+ * (index, sweep number k >= 1, tag << 24 | round, chain id).  A state's
+ * draws are a pure function of (X, y, seed, chain id, starting state), so
+ * runs are bit-reproducible and resumable.
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns an hsp_status and never aborts or throws.
+ *  - Pointers named "device" must be HIP device (or managed) memory of the
+ *    current device; "host" pointers are ordinary host memory.  The library
+ *    never keeps a caller pointer beyond the call that receives it.
+ *  - Matrices are row-major and dense unless stated otherwise.
+ *  - After HSP_EHIP, HSP_ENOTPD or HSP_ERANGE reported by a sweep, the
+ *    state is poisoned: later calls return HSP_EPOISONED until
+ *    hsp_destroy.  hsp_last_error() describes the failure.
+ *  - One state may be used by one host thread at a time.  Independent
+ *    states may be used concurrently.
+ */
+#ifndef HSP_H
+#define HSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hsp_state hsp_state; /* opaque, owned by the library */
+
+typedef enum {
+    HSP_OK = 0,
+    HSP_EINVAL = -1,    /* invalid argument or input data */
+    HSP_ENOMEM = -2,    /* device or host allocation failed */
+    HSP_EHIP = -3,      /* a HIP runtime call failed */
+    HSP_ENOTPD = -4,    /* X^T X + tau^-2 Lambda^-2 was not positive definite */
+    HSP_ERANGE = -5,    /* a draw left the representable range (NaN/inf) or the
+                           requested draws are no longer stored */
+    HSP_EPOISONED = -6  /* an earlier device failure poisoned this state */
+} hsp_status;
+
+typedef enum { HSP_X_F32 = 0, HSP_X_BF16 = 1 } hsp_xtype;
+
+/* Options of hsp_create; hsp_default_options() fills the defaults. */
+typedef struct {
+    uint64_t seed;          /* Philox key (default 1) */
+    uint32_t chain_id;      /* Philox counter word 3 (default 0) */
+    int32_t x_type;         /* storage of X: HSP_X_F32 (default) or HSP_X_BF16
+                               (rounded to nearest even at creation) */
+    int32_t x_on_host;      /* 1: X and y are host pointers; 0 (default): device */
+    int32_t record_lambda;  /* 1: also record lambda^-2 with every kept draw */
+    int64_t thin;           /* keep the draw of every thin-th sweep (default 1) */
+    int64_t max_draws;      /* capacity of the device-resident draw ring
+                               (default 1024); older draws are overwritten */
+    void* hip_stream;       /* hipStream_t to run on; NULL: the library's own */
+    int32_t debug_store_z;  /* 1: keep z, the accepted attempt and X^T z of the
+                               last z step for hsp_get_debug (costs N*8 bytes
+                               of writes per sweep) */
+    int32_t use_graph;      /* 1 (default): replay sweeps from a captured HIP graph */
+} hsp_options;
+
+void hsp_default_options(hsp_options* opt);
+
+/*
+ * Create a sampler state from the design X (N x p float32, row-major,
+ * leading dimension p) and outcomes y (N bytes, each 0 or 1).
+ * X and y are read during the call only; the library keeps its own copy
+ * (rows padded to 16 bytes, converted to bfloat16 if requested).  Computes
+ * G = X^T X once in float64 (Section 5, beta step i) and sets the cold start
+ * of Section 6.1 (beta = 0; lambda = nu = tau = xi = 1).
+ * Errors: HSP_EINVAL if N < 2, p < 2, N >= 2^32, p > hsp_max_p(), a y_i is
+ * not 0/1 or an X entry is not finite; HSP_ENOMEM; HSP_EHIP.
+ */
+hsp_status hsp_create(const float* X, const uint8_t* y, int64_t N, int64_t p,
+                      const hsp_options* opt, hsp_state** out);
+
+/* Largest p supported by this build. */
+int64_t hsp_max_p(void);
+
+/*
+ * Enqueue n_iter full sweeps on the state's stream and return without
+ * waiting.  Sweep k draws, in order: z and lambda^-2 from beta^(k-1), then
+ * tau^-2; then beta, nu^-1 and xi^-1 (Section 5, updates (i)-(ii)), and
+ * records beta, tau^-2 (and lambda^-2 if requested) when k is a multiple of
+ * thin.  Device failures surface at the next synchronising call.
+ * Errors: HSP_EINVAL if n_iter < 0; HSP_EPOISONED; HSP_EHIP.
+ */
+hsp_status hsp_sweep(hsp_state* s, int64_t n_iter);
+
+/* Wait for the state's enqueued work and report device failures
+ * (HSP_ENOTPD, HSP_ERANGE). */
+hsp_status hsp_sync(hsp_state* s);
+
+/*
+ * Copy kept draws [first, first + count) (0-based, in recording order since
+ * creation or the last hsp_set_state) into host buffers: beta (count x p),
+ * tau_m2 (count), lam_m2 (count x p, only if record_lambda, else may be
+ * NULL).  Synchronises first.  *n_out receives the number of draws recorded
+ * so far.  Errors: HSP_ERANGE if a requested draw was overwritten or not yet
+ * recorded; device failures as hsp_sync.
+ */
+hsp_status hsp_draws(hsp_state* s, double* beta, double* tau_m2, double* lam_m2,
+                     int64_t first, int64_t count, int64_t* n_out);
+
+/* Release every resource of the state (waits for its work first). */
+hsp_status hsp_destroy(hsp_state* s);
+
+/* Text of the last failure on this state (never NULL); for a NULL state,
+ * the last failure of hsp_create on this thread. */
+const char* hsp_last_error(const hsp_state* s);
+
+/* ---- Markov state: checkpoint / resume and test hooks --------------------- */
+/* Copy the Markov state to host buffers (beta, lam_m2, nu_m1: p doubles;
+ * any pointer may be NULL).  Synchronises. */
+hsp_status hsp_get_state(hsp_state* s, double* beta, double* lam_m2, double* nu_m1,
+                         double* tau_m2, double* xi_m1, uint64_t* sweep);
+/* Overwrite the Markov state from host buffers; sweep is the number of
+ * completed sweeps (the next sweep uses counter k = sweep + 1).  Resets the
+ * draw count.  Errors: HSP_EINVAL for a negative or non-finite entry of
+ * lam_m2, nu_m1, tau_m2, xi_m1 or a non-finite beta. */
+hsp_status hsp_set_state(hsp_state* s, const double* beta, const double* lam_m2,
+                         const double* nu_m1, double tau_m2, double xi_m1, uint64_t sweep);
+
+/* Steps for hsp_step (bitmask). */
+enum {
+    HSP_STEP_Z = 1,       /* z | beta and b = X^T z (Section 5, z step; beta step vi) */
+    HSP_STEP_LAMBDA = 2,  /* lambda^-2 | beta, nu, tau */
+    HSP_STEP_TAU = 4,     /* tau^-2 | lambda, beta, xi */
+    HSP_STEP_BETA = 8,    /* beta | b, lambda, tau (Section 5, beta steps ii-viii) */
+    HSP_STEP_NUXI = 16,   /* nu^-1 | lambda and xi^-1 | tau */
+    HSP_STEP_ADVANCE = 32 /* then count the sweep as completed */
+};
+/* Run the selected conditionals once, in the sweep's order, with counter
+ * k = (completed sweeps) + 1, without recording a draw.  Synchronises. */
+hsp_status hsp_step(hsp_state* s, uint32_t which);
+
+/* Debug outputs of the last z step (needs debug_store_z): z (N floats),
+ * attempt (N int32: 0-based index of the accepted proposal, bit 30 set for
+ * the Gaussian branch), b = X^T z (p doubles).  NULL skips an output. */
+hsp_status hsp_get_debug(hsp_state* s, float* z, int32_t* attempt, double* b);
+
+/* G = X^T X (p x p doubles, host). */
+hsp_status hsp_get_gram(hsp_state* s, double* G);
+
+/* Counters since creation: number of lambda rates clamped up to DBL_MIN and
+ * the largest number of truncated-normal proposals any row needed. */
+hsp_status hsp_get_counters(hsp_state* s, uint64_t* lambda_clamps, uint32_t* max_attempts);
+
+/* Timing of the kernels of the last sweeps enqueued by hsp_sweep, measured
+ * with HIP events on the state's stream: mean milliseconds per sweep of the
+ * z pass (the dominant N x p kernel) and of the whole sweep.  Enable with
+ * hsp_set_timing(s, 1) before hsp_sweep (sweeps then run without a graph). */
+hsp_status hsp_set_timing(hsp_state* s, int32_t enable);
+hsp_status hsp_get_timing(hsp_state* s, double* zpass_ms, double* sweep_ms, int64_t* n_sweeps);
+
+/* Philox4x32-10 on the device: out[4i..4i+3] = Philox(ctr[4i..4i+3], key =
+ * seed).  ctr and out are host arrays of 4n words.  Test hook for the
+ * generator's bit-exactness. */
+hsp_status hsp_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

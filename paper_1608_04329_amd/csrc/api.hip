@@ -1,0 +1,604 @@
+// C ABI of the sampler: state management, the sweep schedule, graphs and
+// the device-resident draw ring.  See include/hsp.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hsp.h"
+#include "hsp_internal.hpp"
+
+using namespace hsp;
+
+namespace {
+thread_local std::string g_create_error;
+}
+
+struct hsp_state {
+    int device = 0;
+    int num_cus = 0;
+    size_t max_lds = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hsp_options opt{};
+    XLayout x{};
+    void* Xbuf = nullptr;
+    uint8_t* y = nullptr;
+    Ctrl* ctrl = nullptr;
+    double *beta = nullptr, *lam = nullptr, *nu = nullptr, *tau = nullptr, *xi = nullptr;
+    double *b = nullptr, *G = nullptr, *A = nullptr, *Ud = nullptr, *vec = nullptr;
+    double* partial = nullptr;
+    float* beta32 = nullptr;
+    float* zdbg = nullptr;
+    int32_t* adbg = nullptr;
+    double *ring_beta = nullptr, *ring_tau = nullptr, *ring_lam = nullptr;
+    ZPassPlan plan{};
+    uint64_t sweeps_done = 0;  // host mirror of ctrl->sweep
+    uint64_t draw_base = 0;    // host mirror of ctrl->draw_base
+    std::string err;
+    bool poisoned = false;
+    hipGraphExec_t graph_full = nullptr;  // one whole sweep, recording
+    hipGraphExec_t graph_rest = nullptr;  // the sweep without the z pass
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // per timed sweep: z start, z end, sweep end
+    hipEvent_t ev_first = nullptr;
+    int64_t timed_sweeps = 0;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess) return fail_hip(s, #expr, e_);                          \
+    } while (0)
+
+hsp_status fail(hsp_state* s, hsp_status code, const std::string& msg) {
+    if (s) {
+        s->err = msg;
+        if (code == HSP_EHIP || code == HSP_ENOTPD || code == HSP_ERANGE) s->poisoned = true;
+    } else {
+        g_create_error = msg;
+    }
+    return code;
+}
+
+hsp_status fail_hip(hsp_state* s, const char* what, hipError_t e) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory) return fail(s, HSP_ENOMEM, m);
+    return fail(s, HSP_EHIP, m);
+}
+
+template <typename T>
+hipError_t dalloc(T** p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    return hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
+}
+
+PState pstate(hsp_state* s) {
+    PState p;
+    p.p = s->x.p;
+    p.beta = s->beta;
+    p.beta32 = s->beta32;
+    p.lam_m2 = s->lam;
+    p.nu_m1 = s->nu;
+    p.tau_m2 = s->tau;
+    p.xi_m1 = s->xi;
+    p.b = s->b;
+    p.G = s->G;
+    p.A = s->A;
+    p.Ud = s->Ud;
+    p.vec = s->vec;
+    p.ctrl = s->ctrl;
+    p.seed = s->opt.seed;
+    p.chain = s->opt.chain_id;
+    p.small_lds_ok = beta_small_fits(s->x.p, s->max_lds) ? 1 : 0;
+    return p;
+}
+
+ZPassArgs zargs(hsp_state* s) {
+    ZPassArgs a;
+    a.x = s->x;
+    a.y = s->y;
+    a.beta32 = s->beta32;
+    a.ctrl = s->ctrl;
+    a.seed = s->opt.seed;
+    a.chain = s->opt.chain_id;
+    a.partial = s->partial;
+    a.zdbg = s->opt.debug_store_z ? s->zdbg : nullptr;
+    a.adbg = s->opt.debug_store_z ? s->adbg : nullptr;
+    return a;
+}
+
+// The sweep's kernels after the z pass: b = X^T z, lambda^-2, tau^-2, beta,
+// nu^-1 and xi^-1, recording, sweep counter.
+hipError_t enqueue_rest(hsp_state* s, hipStream_t st, bool record) {
+    const PState ps = pstate(s);
+    hipError_t e;
+    if ((e = reduce_cols_launch(s->partial, s->plan.blocks, s->x.ld, s->x.p, s->b, st))) return e;
+    if ((e = lambda_launch(ps, st))) return e;
+    if ((e = tau_launch(ps, st))) return e;
+    if ((e = beta_launch(ps, st))) return e;
+    if ((e = nuxi_launch(ps, st))) return e;
+    if (record) {
+        if ((e = record_launch(ps, s->ring_beta, s->ring_tau, s->ring_lam, (uint32_t)s->opt.thin,
+                               (uint32_t)s->opt.max_draws, st)))
+            return e;
+    }
+    return advance_launch(s->ctrl, st);
+}
+
+hipError_t enqueue_sweep(hsp_state* s, hipStream_t st) {
+    hipError_t e = zpass_launch(zargs(s), s->plan, st);
+    if (e) return e;
+    return enqueue_rest(s, st, true);
+}
+
+hipError_t capture(hsp_state* s, bool full, hipGraphExec_t* out) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+    if (e) return e;
+    hipError_t e2 = full ? enqueue_sweep(s, s->stream) : enqueue_rest(s, s->stream, true);
+    e = hipStreamEndCapture(s->stream, &g);
+    if (e2) { if (g) (void)hipGraphDestroy(g); return e2; }
+    if (e) return e;
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e;
+}
+
+hsp_status check_device_flags(hsp_state* s) {
+    Ctrl c;
+    HIP_TRY(hipMemcpy(&c, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    if (c.err & kErrNotPD) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf,
+                      "X^T X + tau^-2 Lambda^-2 is not positive definite (pivot %d) at sweep %u",
+                      c.chol_info, c.sweep + 1);
+        return fail(s, HSP_ENOTPD, buf);
+    }
+    if (c.err & kErrTnCap)
+        return fail(s, HSP_ERANGE, "a truncated-normal row reached the proposal cap (non-finite X beta)");
+    if (c.err & kErrNonFinite) return fail(s, HSP_ERANGE, "a draw of beta, lambda or tau was not finite");
+    return HSP_OK;
+}
+
+hsp_status sync_state(hsp_state* s) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return check_device_flags(s);
+}
+
+void free_state(hsp_state* s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    if (s->graph_full) (void)hipGraphExecDestroy(s->graph_full);
+    if (s->graph_rest) (void)hipGraphExecDestroy(s->graph_rest);
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    if (s->ev_first) (void)hipEventDestroy(s->ev_first);
+    void* bufs[] = {s->Xbuf, s->y, s->ctrl, s->beta, s->lam, s->nu, s->tau, s->xi, s->b, s->G,
+                    s->A, s->Ud, s->vec, s->partial, s->beta32, s->zdbg, s->adbg, s->ring_beta,
+                    s->ring_tau, s->ring_lam};
+    for (void* p : bufs)
+        if (p) (void)hipFree(p);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+hsp_status upload_state(hsp_state* s, const double* beta, const double* lam, const double* nu,
+                        double tau, double xi) {
+    const uint32_t p = s->x.p;
+    std::vector<float> b32(s->x.ld, 0.0f);
+    for (uint32_t j = 0; j < p; ++j) b32[j] = (float)beta[j];
+    HIP_TRY(hipMemcpy(s->beta, beta, p * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->beta32, b32.data(), s->x.ld * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->lam, lam, p * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->nu, nu, p * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->tau, &tau, sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->xi, &xi, sizeof(double), hipMemcpyHostToDevice));
+    return HSP_OK;
+}
+
+hsp_status set_counters(hsp_state* s, uint64_t sweep) {
+    Ctrl c;
+    HIP_TRY(hipMemcpy(&c, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    c.sweep = (uint32_t)sweep;
+    c.draw_base = (uint32_t)sweep;
+    HIP_TRY(hipMemcpy(s->ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice));
+    s->sweeps_done = sweep;
+    s->draw_base = sweep;
+    return HSP_OK;
+}
+
+hsp_status create_impl(hsp_state* s, const float* X, const uint8_t* y, int64_t N, int64_t p) {
+    HIP_TRY(hipGetDevice(&s->device));
+    HIP_TRY(hipDeviceGetAttribute(&s->num_cus, hipDeviceAttributeMultiprocessorCount, s->device));
+    {
+        int lds = 0;
+        HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device));
+        s->max_lds = (size_t)lds;
+        if (pside_prepare(s->max_lds) != hipSuccess) {
+            (void)hipGetLastError();
+            s->max_lds = 65536;
+        }
+    }
+    if (s->opt.hip_stream) {
+        s->stream = static_cast<hipStream_t>(s->opt.hip_stream);
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+        s->own_stream = true;
+    }
+    const int xt = s->opt.x_type;
+    const uint32_t align = xt == HSP_X_F32 ? 4 : 8;
+    const uint32_t ld = (uint32_t)((p + align - 1) / align * align);
+    const size_t esz = xt == HSP_X_F32 ? 4 : 2;
+    HIP_TRY(hipMalloc(&s->Xbuf, (size_t)N * ld * esz));
+    s->x.X = s->Xbuf;
+    s->x.xtype = xt;
+    s->x.N = (uint32_t)N;
+    s->x.p = (uint32_t)p;
+    s->x.ld = ld;
+    HIP_TRY(dalloc(&s->y, (size_t)N));
+    HIP_TRY(dalloc(&s->ctrl, 1));
+    HIP_TRY(hipMemsetAsync(s->ctrl, 0, sizeof(Ctrl), s->stream));
+    const hipMemcpyKind kind = s->opt.x_on_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+
+    // X into the library layout
+    if (xt == HSP_X_F32 && ld == (uint32_t)p) {
+        HIP_TRY(hipMemcpyAsync(s->Xbuf, X, (size_t)N * p * 4, kind, s->stream));
+    } else if (!s->opt.x_on_host) {
+        HIP_TRY(pack_x_launch(X, s->x, s->stream));
+    } else {
+        float* stage = nullptr;
+        HIP_TRY(dalloc(&stage, (size_t)N * p));
+        hipError_t e = hipMemcpyAsync(stage, X, (size_t)N * p * 4, kind, s->stream);
+        if (!e) e = pack_x_launch(stage, s->x, s->stream);
+        if (!e) e = hipStreamSynchronize(s->stream);
+        (void)hipFree(stage);
+        HIP_TRY(e);
+    }
+    HIP_TRY(hipMemcpyAsync(s->y, y, (size_t)N, kind, s->stream));
+    HIP_TRY(validate_launch(s->x, s->y, s->ctrl, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    {
+        Ctrl c;
+        HIP_TRY(hipMemcpy(&c, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+        if (c.err & kErrInput)
+            return fail(nullptr, HSP_EINVAL,
+                        "y must hold only 0/1 and X must be finite (also after bfloat16 rounding)");
+    }
+
+    // p-sized state
+    HIP_TRY(dalloc(&s->beta, p));
+    HIP_TRY(dalloc(&s->beta32, ld));
+    HIP_TRY(dalloc(&s->lam, p));
+    HIP_TRY(dalloc(&s->nu, p));
+    HIP_TRY(dalloc(&s->tau, 1));
+    HIP_TRY(dalloc(&s->xi, 1));
+    HIP_TRY(dalloc(&s->b, p));
+    HIP_TRY(dalloc(&s->G, (size_t)p * p));
+    HIP_TRY(dalloc(&s->A, (size_t)p * p));
+    const size_t nt = ((size_t)p + 63) / 64;
+    HIP_TRY(dalloc(&s->Ud, nt * 64 * 64));
+    HIP_TRY(dalloc(&s->vec, 4 * (size_t)p));
+    HIP_TRY(hipMemsetAsync(s->A, 0, (size_t)p * p * sizeof(double), s->stream));
+
+    // G = X^T X
+    {
+        double* work = nullptr;
+        HIP_TRY(dalloc(&work, gram_work_doubles(s->x, s->num_cus)));
+        hipError_t e = gram_launch(s->x, s->G, work, s->num_cus, s->stream);
+        if (!e) e = hipStreamSynchronize(s->stream);
+        (void)hipFree(work);
+        HIP_TRY(e);
+    }
+
+    s->plan = zpass_plan(s->x, s->num_cus);
+    HIP_TRY(dalloc(&s->partial, (size_t)s->plan.blocks * ld));
+    if (s->opt.debug_store_z) {
+        HIP_TRY(dalloc(&s->zdbg, (size_t)N));
+        HIP_TRY(dalloc(&s->adbg, (size_t)N));
+        HIP_TRY(hipMemsetAsync(s->zdbg, 0, (size_t)N * sizeof(float), s->stream));
+        HIP_TRY(hipMemsetAsync(s->adbg, 0, (size_t)N * sizeof(int32_t), s->stream));
+    }
+    const size_t cap = (size_t)s->opt.max_draws;
+    HIP_TRY(dalloc(&s->ring_beta, cap * p));
+    HIP_TRY(dalloc(&s->ring_tau, cap));
+    if (s->opt.record_lambda) HIP_TRY(dalloc(&s->ring_lam, cap * p));
+
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    // cold start (Section 6.1)
+    std::vector<double> zeros(p, 0.0), ones(p, 1.0);
+    hsp_status st = upload_state(s, zeros.data(), ones.data(), ones.data(), 1.0, 1.0);
+    if (st) return st;
+    st = set_counters(s, 0);
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return HSP_OK;
+}
+
+bool finite_nonneg(const double* v, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i]) || v[i] < 0.0) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hsp_default_options(hsp_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->seed = 1;
+    o->chain_id = 0;
+    o->x_type = HSP_X_F32;
+    o->x_on_host = 0;
+    o->record_lambda = 0;
+    o->thin = 1;
+    o->max_draws = 1024;
+    o->hip_stream = nullptr;
+    o->debug_store_z = 0;
+    o->use_graph = 1;
+}
+
+int64_t hsp_max_p(void) { return kMaxP; }
+
+hsp_status hsp_create(const float* X, const uint8_t* y, int64_t N, int64_t p,
+                      const hsp_options* opt, hsp_state** out) {
+    if (!out) return fail(nullptr, HSP_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (!X || !y) return fail(nullptr, HSP_EINVAL, "X and y must not be NULL");
+    if (N < 2) return fail(nullptr, HSP_EINVAL, "N must be at least 2");
+    if (p < 2) return fail(nullptr, HSP_EINVAL, "p must be at least 2");
+    if (N >= (int64_t(1) << 32) - 64) return fail(nullptr, HSP_EINVAL, "N must be below 2^32");
+    if (p > kMaxP) return fail(nullptr, HSP_EINVAL, "p exceeds hsp_max_p()");
+    hsp_state* s = new (std::nothrow) hsp_state();
+    if (!s) return fail(nullptr, HSP_ENOMEM, "host allocation failed");
+    if (opt) s->opt = *opt;
+    else hsp_default_options(&s->opt);
+    if (s->opt.x_type != HSP_X_F32 && s->opt.x_type != HSP_X_BF16) {
+        delete s;
+        return fail(nullptr, HSP_EINVAL, "x_type must be HSP_X_F32 or HSP_X_BF16");
+    }
+    if (s->opt.thin < 1 || s->opt.max_draws < 1 || s->opt.max_draws > (int64_t(1) << 30)) {
+        delete s;
+        return fail(nullptr, HSP_EINVAL, "thin must be >= 1 and max_draws in [1, 2^30]");
+    }
+    hsp_status st = create_impl(s, X, y, N, p);
+    if (st != HSP_OK) {
+        if (!s->err.empty()) g_create_error = s->err;
+        free_state(s);
+        return st;
+    }
+    *out = s;
+    return HSP_OK;
+}
+
+hsp_status hsp_sweep(hsp_state* s, int64_t n) {
+    if (!s) return HSP_EINVAL;
+    if (s->poisoned) return HSP_EPOISONED;
+    if (n < 0) return fail(s, HSP_EINVAL, "n_iter must be >= 0");
+    if (s->sweeps_done + (uint64_t)n >= (uint64_t(1) << 32) - 1)
+        return fail(s, HSP_EINVAL, "the sweep counter would exceed 2^32");
+    if (s->timing) {
+        if (!s->graph_rest && s->opt.use_graph) {
+            hipError_t e = capture(s, false, &s->graph_rest);
+            if (e) return fail_hip(s, "graph capture", e);
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            hipEvent_t e3[3];
+            for (auto& e : e3) HIP_TRY(hipEventCreate(&e));
+            for (auto& e : e3) s->ev.push_back(e);
+            HIP_TRY(hipEventRecord(e3[0], s->stream));
+            HIP_TRY(zpass_launch(zargs(s), s->plan, s->stream));
+            HIP_TRY(hipEventRecord(e3[1], s->stream));
+            if (s->graph_rest) HIP_TRY(hipGraphLaunch(s->graph_rest, s->stream));
+            else HIP_TRY(enqueue_rest(s, s->stream, true));
+            HIP_TRY(hipEventRecord(e3[2], s->stream));
+        }
+        s->timed_sweeps += n;
+    } else if (s->opt.use_graph) {
+        if (!s->graph_full) {
+            hipError_t e = capture(s, true, &s->graph_full);
+            if (e) return fail_hip(s, "graph capture", e);
+        }
+        for (int64_t i = 0; i < n; ++i) HIP_TRY(hipGraphLaunch(s->graph_full, s->stream));
+    } else {
+        for (int64_t i = 0; i < n; ++i) HIP_TRY(enqueue_sweep(s, s->stream));
+    }
+    s->sweeps_done += (uint64_t)n;
+    return HSP_OK;
+}
+
+hsp_status hsp_sync(hsp_state* s) {
+    if (!s) return HSP_EINVAL;
+    if (s->poisoned) return HSP_EPOISONED;
+    return sync_state(s);
+}
+
+hsp_status hsp_draws(hsp_state* s, double* beta, double* tau_m2, double* lam_m2, int64_t first,
+                     int64_t count, int64_t* n_out) {
+    if (!s) return HSP_EINVAL;
+    if (s->poisoned) return HSP_EPOISONED;
+    hsp_status st = sync_state(s);
+    if (st) return st;
+    const int64_t recorded = (int64_t)((s->sweeps_done - s->draw_base) / (uint64_t)s->opt.thin);
+    if (n_out) *n_out = recorded;
+    if (count == 0) return HSP_OK;
+    if (first < 0 || count < 0 || first + count > recorded || first < recorded - s->opt.max_draws)
+        return fail(s, HSP_EINVAL, "requested draws are not stored (range or overwritten)");
+    if (lam_m2 && !s->ring_lam) return fail(s, HSP_EINVAL, "lambda was not recorded");
+    const int64_t cap = s->opt.max_draws;
+    const size_t p = s->x.p;
+    for (int64_t d = first; d < first + count;) {
+        const int64_t slot = d % cap;
+        const int64_t run = std::min(first + count - d, cap - slot);
+        const int64_t o = d - first;
+        if (beta)
+            HIP_TRY(hipMemcpy(beta + o * p, s->ring_beta + slot * p, run * p * sizeof(double),
+                              hipMemcpyDeviceToHost));
+        if (tau_m2)
+            HIP_TRY(hipMemcpy(tau_m2 + o, s->ring_tau + slot, run * sizeof(double),
+                              hipMemcpyDeviceToHost));
+        if (lam_m2)
+            HIP_TRY(hipMemcpy(lam_m2 + o * p, s->ring_lam + slot * p, run * p * sizeof(double),
+                              hipMemcpyDeviceToHost));
+        d += run;
+    }
+    return HSP_OK;
+}
+
+hsp_status hsp_destroy(hsp_state* s) {
+    free_state(s);
+    return HSP_OK;
+}
+
+const char* hsp_last_error(const hsp_state* s) {
+    if (!s) return g_create_error.c_str();
+    return s->err.c_str();
+}
+
+hsp_status hsp_get_state(hsp_state* s, double* beta, double* lam_m2, double* nu_m1,
+                         double* tau_m2, double* xi_m1, uint64_t* sweep) {
+    if (!s) return HSP_EINVAL;
+    if (s->poisoned) return HSP_EPOISONED;
+    hsp_status st = sync_state(s);
+    if (st) return st;
+    const size_t p = s->x.p;
+    if (beta) HIP_TRY(hipMemcpy(beta, s->beta, p * sizeof(double), hipMemcpyDeviceToHost));
+    if (lam_m2) HIP_TRY(hipMemcpy(lam_m2, s->lam, p * sizeof(double), hipMemcpyDeviceToHost));
+    if (nu_m1) HIP_TRY(hipMemcpy(nu_m1, s->nu, p * sizeof(double), hipMemcpyDeviceToHost));
+    if (tau_m2) HIP_TRY(hipMemcpy(tau_m2, s->tau, sizeof(double), hipMemcpyDeviceToHost));
+    if (xi_m1) HIP_TRY(hipMemcpy(xi_m1, s->xi, sizeof(double), hipMemcpyDeviceToHost));
+    if (sweep) *sweep = s->sweeps_done;
+    return HSP_OK;
+}
+
+hsp_status hsp_set_state(hsp_state* s, const double* beta, const double* lam_m2,
+                         const double* nu_m1, double tau_m2, double xi_m1, uint64_t sweep) {
+    if (!s) return HSP_EINVAL;
+    if (s->poisoned) return HSP_EPOISONED;
+    if (!beta || !lam_m2 || !nu_m1) return fail(s, HSP_EINVAL, "state vectors must not be NULL");
+    const int64_t p = s->x.p;
+    for (int64_t j = 0; j < p; ++j)
+        if (!std::isfinite(beta[j])) return fail(s, HSP_EINVAL, "beta must be finite");
+    if (!finite_nonneg(lam_m2, p) || !finite_nonneg(nu_m1, p) || !finite_nonneg(&tau_m2, 1) ||
+        !finite_nonneg(&xi_m1, 1))
+        return fail(s, HSP_EINVAL, "lam_m2, nu_m1, tau_m2, xi_m1 must be finite and >= 0");
+    if (sweep >= (uint64_t(1) << 32) - 1) return fail(s, HSP_EINVAL, "sweep must be below 2^32");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    hsp_status st = upload_state(s, beta, lam_m2, nu_m1, tau_m2, xi_m1);
+    if (st) return st;
+    return set_counters(s, sweep);
+}
+
+hsp_status hsp_step(hsp_state* s, uint32_t which) {
+    if (!s) return HSP_EINVAL;
+    if (s->poisoned) return HSP_EPOISONED;
+    const PState ps = pstate(s);
+    hipStream_t st = s->stream;
+    if (which & HSP_STEP_Z) {
+        HIP_TRY(zpass_launch(zargs(s), s->plan, st));
+        HIP_TRY(reduce_cols_launch(s->partial, s->plan.blocks, s->x.ld, s->x.p, s->b, st));
+    }
+    if (which & HSP_STEP_LAMBDA) HIP_TRY(lambda_launch(ps, st));
+    if (which & HSP_STEP_TAU) HIP_TRY(tau_launch(ps, st));
+    if (which & HSP_STEP_BETA) HIP_TRY(beta_launch(ps, st));
+    if (which & HSP_STEP_NUXI) HIP_TRY(nuxi_launch(ps, st));
+    if (which & HSP_STEP_ADVANCE) {
+        HIP_TRY(advance_launch(s->ctrl, st));
+        s->sweeps_done += 1;
+        s->draw_base += 1;  // hsp_step never records a draw
+        Ctrl c;
+        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(hipMemcpy(&c, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+        c.draw_base = (uint32_t)s->draw_base;
+        HIP_TRY(hipMemcpy(s->ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice));
+    }
+    return sync_state(s);
+}
+
+hsp_status hsp_get_debug(hsp_state* s, float* z, int32_t* attempt, double* b) {
+    if (!s) return HSP_EINVAL;
+    if (s->poisoned) return HSP_EPOISONED;
+    if ((z || attempt) && !s->opt.debug_store_z)
+        return fail(s, HSP_EINVAL, "create the state with debug_store_z = 1");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const size_t N = s->x.N;
+    if (z) HIP_TRY(hipMemcpy(z, s->zdbg, N * sizeof(float), hipMemcpyDeviceToHost));
+    if (attempt) HIP_TRY(hipMemcpy(attempt, s->adbg, N * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (b) HIP_TRY(hipMemcpy(b, s->b, s->x.p * sizeof(double), hipMemcpyDeviceToHost));
+    return HSP_OK;
+}
+
+hsp_status hsp_get_gram(hsp_state* s, double* G) {
+    if (!s || !G) return HSP_EINVAL;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipMemcpy(G, s->G, (size_t)s->x.p * s->x.p * sizeof(double), hipMemcpyDeviceToHost));
+    return HSP_OK;
+}
+
+hsp_status hsp_get_counters(hsp_state* s, uint64_t* clamps, uint32_t* max_attempts) {
+    if (!s) return HSP_EINVAL;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    Ctrl c;
+    HIP_TRY(hipMemcpy(&c, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    if (clamps) *clamps = c.clamps;
+    if (max_attempts) *max_attempts = c.max_attempts;
+    return HSP_OK;
+}
+
+hsp_status hsp_set_timing(hsp_state* s, int32_t enable) {
+    if (!s) return HSP_EINVAL;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    s->ev.clear();
+    s->timed_sweeps = 0;
+    s->timing = enable != 0;
+    return HSP_OK;
+}
+
+hsp_status hsp_get_timing(hsp_state* s, double* zpass_ms, double* sweep_ms, int64_t* n) {
+    if (!s) return HSP_EINVAL;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    double zsum = 0.0;
+    const size_t ns = s->ev.size() / 3;
+    for (size_t i = 0; i < ns; ++i) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, s->ev[3 * i], s->ev[3 * i + 1]));
+        zsum += ms;
+    }
+    double total = 0.0;
+    if (ns) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, s->ev[0], s->ev[3 * (ns - 1) + 2]));
+        total = ms;
+    }
+    if (zpass_ms) *zpass_ms = ns ? zsum / ns : 0.0;
+    if (sweep_ms) *sweep_ms = ns ? total / ns : 0.0;
+    if (n) *n = (int64_t)ns;
+    return HSP_OK;
+}
+
+hsp_status hsp_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out) {
+    hsp_state* s = nullptr;
+    if (!ctr || !out || n < 0 || n > (int64_t(1) << 28)) return fail(nullptr, HSP_EINVAL, "bad arguments");
+    if (n == 0) return HSP_OK;
+    uint32_t *dc = nullptr, *dout = nullptr;
+    HIP_TRY(dalloc(&dc, 4 * (size_t)n));
+    hipError_t e = dalloc(&dout, 4 * (size_t)n);
+    if (!e) e = hipMemcpy(dc, ctr, 16 * (size_t)n, hipMemcpyHostToDevice);
+    if (!e) e = philox_test_launch(seed, dc, (uint32_t)n, dout, nullptr);
+    if (!e) e = hipDeviceSynchronize();
+    if (!e) e = hipMemcpy(out, dout, 16 * (size_t)n, hipMemcpyDeviceToHost);
+    (void)hipFree(dc);
+    if (dout) (void)hipFree(dout);
+    HIP_TRY(e);
+    return HSP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,301 @@
+// The z pass: one read of X per sweep computes, for every row i,
+//   eta_i = x_i beta                      (Section 5, z step i)
+//   z_i ~ TN(eta_i, 1, y_i)               (Section 5, z step ii; Eq. 12)
+//   b += x_i^T z_i                        (Section 5, beta step vi)
+// Rows are full-conditionally independent (Eq. 8), so every row is drawn in
+// parallel.  A wave owns a tile of R consecutive rows held in registers: each
+// lane loads 16-byte vectors of every row (coalesced across the wave), the
+// wave reduces the R dot products, lanes 0..R-1 draw one truncated normal
+// each, and the same registers then feed x_i^T z_i.  X is read from HBM
+// exactly once; eta and z never touch memory.
+//
+// Truncated normal, divergence-free: with y* = 2y - 1 and mu* = y* eta the
+// draw is t ~ N(mu*, 1) restricted to t > 0 and z = y* t (the y* trick of
+// Section 5 removes the sign divergence).  Every proposal evaluates both
+// candidate samplers from the same two uniforms and selects one:
+//   mu* > 0.47  Gaussian rejection: t = mu* + sqrt(-2 ln u1) cos(2 pi u2),
+//               accept if t > 0;
+//   otherwise   Robert (1995) exponential rejection with the optimal rate
+//               theta = (-mu* + sqrt(mu*^2 + 4)) / 2 for the bound -mu* of
+//               t - mu*: t = -ln(u1) / theta, accept if
+//               u2 < exp(-(t - mu* - theta)^2 / 2) = exp(-(t - 1/theta)^2 / 2)
+//               (theta (theta + mu*) = 1 makes the second form exact and free
+//               of cancellation).
+// So lanes on different branches run the same instructions.  Proposal a of
+// row i uses Philox round a/2 (two proposals per call).
+#include "hsp_internal.hpp"
+#include "philox.hpp"
+
+namespace hsp {
+namespace {
+
+constexpr int kWPB = 4;                 // waves per block
+constexpr int kThreads = kWPB * kWave;  // 256
+constexpr int kRedCols = 1024;          // columns per LDS reduction segment
+
+template <int XT>
+struct XTraits;
+template <>
+struct XTraits<0> {  // float32
+    static constexpr int VEC = 4;
+    static constexpr int BYTES = 4;
+};
+template <>
+struct XTraits<1> {  // bfloat16
+    static constexpr int VEC = 8;
+    static constexpr int BYTES = 2;
+};
+
+__device__ __forceinline__ uint32_t word_of(const uint4& v, int i) {
+    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+
+template <int XT>
+__device__ __forceinline__ float xelem(const uint4& v, int e) {
+    if constexpr (XT == 0) {
+        return __uint_as_float(word_of(v, e));
+    } else {
+        const uint32_t w = word_of(v, e >> 1);
+        return (e & 1) ? __uint_as_float(w & 0xFFFF0000u) : __uint_as_float(w << 16);
+    }
+}
+
+// One proposal from the uniforms (ua, ub): both candidates, one selected.
+__device__ __forceinline__ void tn_candidate(float mu, bool gauss, float theta, float inv_theta,
+                                             float ua, float ub, float& t, bool& acc) {
+    const float L = -logf(ua);
+    const float tg = fmaf(sqrtf(2.0f * L), cospif(2.0f * ub), mu);
+    const float tr = L / theta;
+    const float d = tr - inv_theta;
+    const float rho = expf(-0.5f * d * d);
+    t = gauss ? tg : tr;
+    acc = gauss ? (tg > 0.0f) : (ub < rho);
+}
+
+template <int XT, int KC, int R>
+__global__ __launch_bounds__(kThreads) void zpass_kernel(ZPassArgs a) {
+    constexpr int VEC = XTraits<XT>::VEC;
+    constexpr int EB = XTraits<XT>::BYTES;
+    constexpr int CW = kWave * VEC;  // columns covered by one wave-wide 16-byte load
+    __shared__ double red[kWPB * kRedCols];
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const uint32_t ld = a.x.ld;
+    const uint32_t N = a.x.N;
+    const uint32_t ksweep = a.ctrl->sweep + 1u;
+    const char* __restrict__ Xb = static_cast<const char*>(a.x.X);
+    const size_t row_bytes = (size_t)ld * EB;
+
+    float bl[KC][VEC];
+    double bacc[KC][VEC];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const uint32_t col = kc * CW + lane * VEC + e;
+            bl[kc][e] = col < ld ? a.beta32[col] : 0.0f;
+            bacc[kc][e] = 0.0;
+        }
+
+    const uint32_t n_tiles = (N + R - 1) / R;
+    const uint32_t W = gridDim.x * kWPB;
+    uint32_t maxatt = 0;
+    bool capped = false;
+
+    for (uint32_t t = blockIdx.x * kWPB + wave; t < n_tiles; t += W) {
+        const uint32_t row0 = t * R;
+        uint4 xr[R][KC];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                const uint32_t row = row0 + r;
+                const uint32_t col = kc * CW + lane * VEC;
+                if (row < N && col < ld)
+                    xr[r][kc] = *reinterpret_cast<const uint4*>(Xb + row * row_bytes + (size_t)col * EB);
+                else
+                    xr[r][kc] = make_uint4(0u, 0u, 0u, 0u);
+            }
+
+        // eta for the R rows of the tile, reduced across the wave
+        float s[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc = fmaf(xelem<XT>(xr[r][kc], e), bl[kc][e], acc);
+            s[r] = acc;
+        }
+#pragma unroll
+        for (int off = kWave / 2; off >= 1; off >>= 1)
+#pragma unroll
+            for (int r = 0; r < R; ++r) s[r] += __shfl_xor(s[r], off);
+        float eta = s[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r) eta = (lane == r) ? s[r] : eta;
+
+        // lane r < R draws z for row row0 + r
+        const uint32_t row = row0 + (uint32_t)lane;
+        const bool active = lane < R && row < N;
+        const float ys = (active && a.y[row]) ? 1.0f : -1.0f;
+        const float mu = ys * eta;
+        const bool gauss = mu > 0.47f;
+        const float den = sqrtf(fmaf(mu, mu, 4.0f)) - mu;  // 2 theta
+        const float theta = 0.5f * den;
+        const float inv_theta = 2.0f / den;
+        float zval = 0.0f;
+        int32_t att = -1;
+        bool done = !active;
+        for (uint32_t round = 0; __ballot(!done) != 0ull; ++round) {
+            if (!done) {
+                const Words4 w = draw_words(a.seed, row, ksweep, kTagZ, round, a.chain);
+                float t0, t1;
+                bool a0, a1;
+                tn_candidate(mu, gauss, theta, inv_theta, u01f(w.w0), u01f(w.w1), t0, a0);
+                tn_candidate(mu, gauss, theta, inv_theta, u01f(w.w2), u01f(w.w3), t1, a1);
+                if (a0) {
+                    zval = ys * t0;
+                    att = (int32_t)(2 * round);
+                    done = true;
+                } else if (a1) {
+                    zval = ys * t1;
+                    att = (int32_t)(2 * round + 1);
+                    done = true;
+                } else if (round + 1 >= kMaxRounds) {
+                    zval = __builtin_nanf("");
+                    done = true;
+                    capped = true;
+                }
+            }
+        }
+        if (active) {
+            maxatt = max(maxatt, (uint32_t)(att + 1));
+            if (a.zdbg) {
+                a.zdbg[row] = zval;
+                a.adbg[row] = att | (gauss ? (1 << 30) : 0);
+            }
+        }
+
+        // b += x_r^T z_r for the tile: R-term float sums, then float64
+        float zr[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            zr[r] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zval), r));
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc = fmaf(zr[r], xelem<XT>(xr[r][kc], e), acc);
+                bacc[kc][e] += (double)acc;
+            }
+    }
+
+    // wave statistics
+    uint32_t m = maxatt;
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    const bool anycap = __ballot(capped) != 0ull;
+    if (lane == 0) {
+        if (m) atomicMax(&a.ctrl->max_attempts, m);
+        if (anycap) atomicOr(&a.ctrl->err, kErrTnCap);
+    }
+
+    // block partial of X^T z: the waves' float64 sums added in wave order
+    for (uint32_t seg = 0; seg < ld; seg += kRedCols) {
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const uint32_t col = kc * CW + lane * VEC + e;
+                if (col >= seg && col < seg + kRedCols && col < ld)
+                    red[wave * kRedCols + (col - seg)] = bacc[kc][e];
+            }
+        __syncthreads();
+        for (uint32_t c = threadIdx.x; c < kRedCols && seg + c < ld; c += kThreads) {
+            double v = red[c];
+#pragma unroll
+            for (int w = 1; w < kWPB; ++w) v += red[w * kRedCols + c];
+            a.partial[(size_t)blockIdx.x * ld + seg + c] = v;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void reduce_cols_kernel(const double* __restrict__ partial,
+                                                          int nrows, uint32_t ld, uint32_t p,
+                                                          double* __restrict__ b) {
+    __shared__ double red[16][17];
+    const int tc = threadIdx.x & 15, tr = threadIdx.x >> 4;
+    const uint32_t col = blockIdx.x * 16 + tc;
+    double s = 0.0;
+    if (col < p)
+        for (int r = tr; r < nrows; r += 16) s += partial[(size_t)r * ld + col];
+    red[tr][tc] = s;
+    __syncthreads();
+    if (tr == 0 && col < p) {
+        double t = 0.0;
+        for (int i = 0; i < 16; ++i) t += red[i][tc];
+        b[col] = t;
+    }
+}
+
+template <int XT>
+constexpr int rows_for_chunks(int kc) {
+    return kc <= 4 ? 8 : (kc <= 8 ? 4 : 2);
+}
+
+template <int XT, int KC>
+hipError_t launch_kc(const ZPassArgs& a, int blocks, hipStream_t st) {
+    constexpr int R = rows_for_chunks<XT>(KC);
+    hipLaunchKernelGGL((zpass_kernel<XT, KC, R>), dim3(blocks), dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int XT, int... KCs>
+hipError_t dispatch(const ZPassArgs& a, int kc, int blocks, hipStream_t st,
+                    std::integer_sequence<int, KCs...>) {
+    hipError_t e = hipErrorInvalidValue;
+    ((kc == KCs + 1 ? (e = launch_kc<XT, KCs + 1>(a, blocks, st), 0) : 0), ...);
+    return e;
+}
+
+}  // namespace
+
+ZPassPlan zpass_plan(const XLayout& x, int num_cus) {
+    const int vec = x.xtype == 0 ? 4 : 8;
+    const int cw = kWave * vec;
+    ZPassPlan plan;
+    plan.chunks = (int)((x.ld + cw - 1) / cw);
+    plan.rows_per_wave_tile = x.xtype == 0 ? rows_for_chunks<0>(plan.chunks)
+                                           : rows_for_chunks<1>(plan.chunks);
+    const uint64_t tiles = (x.N + plan.rows_per_wave_tile - 1) / plan.rows_per_wave_tile;
+    const uint64_t need = (tiles + kWPB - 1) / kWPB;
+    int per_cu = 2;
+    if (const char* env = getenv("HSP_ZPASS_BLOCKS_PER_CU")) per_cu = atoi(env) > 0 ? atoi(env) : 2;
+    const uint64_t cap = (uint64_t)num_cus * per_cu;
+    plan.blocks = (int)(need < cap ? need : cap);
+    if (plan.blocks < 1) plan.blocks = 1;
+    return plan;
+}
+
+hipError_t zpass_launch(const ZPassArgs& a, const ZPassPlan& plan, hipStream_t st) {
+    const int max_kc = a.x.xtype == 0 ? kMaxP / (kWave * 4) : kMaxP / (kWave * 8);
+    if (plan.chunks < 1 || plan.chunks > max_kc) return hipErrorInvalidValue;
+    if (a.x.xtype == 0)
+        return dispatch<0>(a, plan.chunks, plan.blocks, st, std::make_integer_sequence<int, 16>{});
+    return dispatch<1>(a, plan.chunks, plan.blocks, st, std::make_integer_sequence<int, 8>{});
+}
+
+hipError_t reduce_cols_launch(const double* partial, int nrows, uint32_t ld, uint32_t p,
+                              double* b, hipStream_t st) {
+    hipLaunchKernelGGL(reduce_cols_kernel, dim3((p + 15) / 16), dim3(256), 0, st, partial, nrows,
+                       ld, p, b);
+    return hipGetLastError();
+}
+
+}  // namespace hsp

@@ -1,0 +1,276 @@
+"""Thin Python binding of the C ABI in include/hsp.h (ctypes).
+
+Argument marshalling only: every step of the sampler runs in the HIP
+library libhsp.so.  The binding refuses to run when the library is missing.
+Device buffers may be torch tensors on the GPU (their data_ptr() is passed);
+host buffers are numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhsp.so")
+
+HSP_OK, HSP_EINVAL, HSP_ENOMEM, HSP_EHIP, HSP_ENOTPD, HSP_ERANGE, HSP_EPOISONED = 0, -1, -2, -3, -4, -5, -6
+HSP_X_F32, HSP_X_BF16 = 0, 1
+HSP_STEP_Z, HSP_STEP_LAMBDA, HSP_STEP_TAU, HSP_STEP_BETA, HSP_STEP_NUXI, HSP_STEP_ADVANCE = 1, 2, 4, 8, 16, 32
+GAUSS_BIT = 1 << 30
+
+STATUS_NAMES = {0: "HSP_OK", -1: "HSP_EINVAL", -2: "HSP_ENOMEM", -3: "HSP_EHIP", -4: "HSP_ENOTPD",
+                -5: "HSP_ERANGE", -6: "HSP_EPOISONED"}
+
+EXPORTS = ["hsp_default_options", "hsp_max_p", "hsp_create", "hsp_sweep", "hsp_sync", "hsp_draws",
+           "hsp_destroy", "hsp_last_error", "hsp_get_state", "hsp_set_state", "hsp_step",
+           "hsp_get_debug", "hsp_get_gram", "hsp_get_counters", "hsp_set_timing",
+           "hsp_get_timing", "hsp_philox"]
+
+
+class hsp_options(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("chain_id", C.c_uint32), ("x_type", C.c_int32),
+                ("x_on_host", C.c_int32), ("record_lambda", C.c_int32), ("thin", C.c_int64),
+                ("max_draws", C.c_int64), ("hip_stream", C.c_void_p), ("debug_store_z", C.c_int32),
+                ("use_graph", C.c_int32)]
+
+
+class HspError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libhsp.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, u64, u32, i32, d = C.c_void_p, C.c_int64, C.c_uint64, C.c_uint32, C.c_int32, C.c_double
+    st = C.c_int
+    L.hsp_default_options.argtypes = [C.POINTER(hsp_options)]
+    L.hsp_default_options.restype = None
+    L.hsp_max_p.restype = i64
+    L.hsp_create.argtypes = [vp, vp, i64, i64, C.POINTER(hsp_options), C.POINTER(vp)]
+    L.hsp_create.restype = st
+    L.hsp_sweep.argtypes = [vp, i64]; L.hsp_sweep.restype = st
+    L.hsp_sync.argtypes = [vp]; L.hsp_sync.restype = st
+    L.hsp_draws.argtypes = [vp, vp, vp, vp, i64, i64, C.POINTER(i64)]; L.hsp_draws.restype = st
+    L.hsp_destroy.argtypes = [vp]; L.hsp_destroy.restype = st
+    L.hsp_last_error.argtypes = [vp]; L.hsp_last_error.restype = C.c_char_p
+    L.hsp_get_state.argtypes = [vp, vp, vp, vp, C.POINTER(d), C.POINTER(d), C.POINTER(u64)]
+    L.hsp_get_state.restype = st
+    L.hsp_set_state.argtypes = [vp, vp, vp, vp, d, d, u64]; L.hsp_set_state.restype = st
+    L.hsp_step.argtypes = [vp, u32]; L.hsp_step.restype = st
+    L.hsp_get_debug.argtypes = [vp, vp, vp, vp]; L.hsp_get_debug.restype = st
+    L.hsp_get_gram.argtypes = [vp, vp]; L.hsp_get_gram.restype = st
+    L.hsp_get_counters.argtypes = [vp, C.POINTER(u64), C.POINTER(u32)]
+    L.hsp_get_counters.restype = st
+    L.hsp_set_timing.argtypes = [vp, i32]; L.hsp_set_timing.restype = st
+    L.hsp_get_timing.argtypes = [vp, C.POINTER(d), C.POINTER(d), C.POINTER(i64)]
+    L.hsp_get_timing.restype = st
+    L.hsp_philox.argtypes = [u64, vp, i64, vp]; L.hsp_philox.restype = st
+    _lib = L
+    return L
+
+
+def _check(code, state=None):
+    if code != HSP_OK:
+        msg = load().hsp_last_error(state)
+        raise HspError(code, msg.decode() if msg else "")
+
+
+def _hp(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+# ---- the C entry points under their own names --------------------------------
+def hsp_default_options():
+    o = hsp_options()
+    load().hsp_default_options(C.byref(o))
+    return o
+
+
+def hsp_max_p():
+    return load().hsp_max_p()
+
+
+def hsp_create(X, y, N, p, opt=None):
+    """X, y: device pointers (int) or, with opt.x_on_host = 1, host pointers."""
+    h = C.c_void_p()
+    code = load().hsp_create(X, y, N, p, C.byref(opt) if opt is not None else None, C.byref(h))
+    _check(code)
+    return h
+
+
+def hsp_sweep(h, n):
+    _check(load().hsp_sweep(h, n), h)
+
+
+def hsp_sync(h):
+    _check(load().hsp_sync(h), h)
+
+
+def hsp_draws(h, first, count, p, lam=False):
+    beta = np.zeros((count, p))
+    tau = np.zeros(count)
+    lamv = np.zeros((count, p)) if lam else None
+    n = C.c_int64(0)
+    _check(load().hsp_draws(h, _hp(beta), _hp(tau), _hp(lamv), first, count, C.byref(n)), h)
+    return (beta, tau, lamv, n.value) if lam else (beta, tau, n.value)
+
+
+def hsp_destroy(h):
+    load().hsp_destroy(h)
+
+
+def hsp_get_state(h, p):
+    beta, lam, nu = np.zeros(p), np.zeros(p), np.zeros(p)
+    tau, xi, sweep = C.c_double(), C.c_double(), C.c_uint64()
+    _check(load().hsp_get_state(h, _hp(beta), _hp(lam), _hp(nu), C.byref(tau), C.byref(xi),
+                                C.byref(sweep)), h)
+    return dict(beta=beta, lam_m2=lam, nu_m1=nu, tau_m2=tau.value, xi_m1=xi.value,
+                sweep=sweep.value)
+
+
+def hsp_set_state(h, beta, lam_m2, nu_m1, tau_m2, xi_m1, sweep):
+    b = np.ascontiguousarray(beta, np.float64)
+    l = np.ascontiguousarray(lam_m2, np.float64)
+    n = np.ascontiguousarray(nu_m1, np.float64)
+    _check(load().hsp_set_state(h, _hp(b), _hp(l), _hp(n), float(tau_m2), float(xi_m1), int(sweep)), h)
+
+
+def hsp_step(h, which):
+    _check(load().hsp_step(h, which), h)
+
+
+def hsp_get_debug(h, N, p):
+    z = np.zeros(N, np.float32)
+    att = np.zeros(N, np.int32)
+    b = np.zeros(p)
+    _check(load().hsp_get_debug(h, _hp(z), _hp(att), _hp(b)), h)
+    return z, att, b
+
+
+def hsp_get_gram(h, p):
+    G = np.zeros((p, p))
+    _check(load().hsp_get_gram(h, _hp(G)), h)
+    return G
+
+
+def hsp_get_counters(h):
+    c, m = C.c_uint64(), C.c_uint32()
+    _check(load().hsp_get_counters(h, C.byref(c), C.byref(m)), h)
+    return c.value, m.value
+
+
+def hsp_set_timing(h, enable):
+    _check(load().hsp_set_timing(h, int(enable)), h)
+
+
+def hsp_get_timing(h):
+    z, s, n = C.c_double(), C.c_double(), C.c_int64()
+    _check(load().hsp_get_timing(h, C.byref(z), C.byref(s), C.byref(n)), h)
+    return z.value, s.value, n.value
+
+
+def hsp_philox(seed, ctr):
+    ctr = np.ascontiguousarray(ctr, np.uint32).reshape(-1, 4)
+    out = np.zeros_like(ctr)
+    _check(load().hsp_philox(seed, _hp(ctr), ctr.shape[0], _hp(out)))
+    return out
+
+
+# ---- convenience wrapper --------------------------------------------------------
+class Sampler:
+    """One Horseshoe Probit chain on the GPU.
+
+    X: (N, p) float32 torch tensor on the GPU, or a numpy array (host copy).
+    y: (N,) uint8 tensor / array with values in {0, 1}.
+    """
+
+    def __init__(self, X, y, seed=1, chain_id=0, x_type="f32", record_lambda=False, thin=1,
+                 max_draws=1024, debug_store_z=False, use_graph=True, stream=None):
+        load()
+        opt = hsp_default_options()
+        opt.seed = seed
+        opt.chain_id = chain_id
+        opt.x_type = {"f32": HSP_X_F32, "bf16": HSP_X_BF16}[x_type]
+        opt.record_lambda = int(record_lambda)
+        opt.thin = thin
+        opt.max_draws = max_draws
+        opt.debug_store_z = int(debug_store_z)
+        opt.use_graph = int(use_graph)
+        if stream is not None:
+            opt.hip_stream = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        if isinstance(X, np.ndarray):
+            X = np.ascontiguousarray(X, np.float32)
+            y = np.ascontiguousarray(y, np.uint8)
+            opt.x_on_host = 1
+            xp, yp = X.ctypes.data, y.ctypes.data
+        else:
+            if not (X.is_cuda and y.is_cuda):
+                raise ValueError("torch inputs must live on the GPU (or pass numpy arrays)")
+            X = X.contiguous()
+            y = y.contiguous()
+            # the library copies X and y on its own stream: finish torch's work first
+            import torch
+            torch.cuda.synchronize(X.device)
+            xp, yp = X.data_ptr(), y.data_ptr()
+        self.N, self.p = int(X.shape[0]), int(X.shape[1])
+        self.record_lambda = record_lambda
+        self.h = hsp_create(xp, yp, self.N, self.p, opt)
+
+    def close(self):
+        if self.h:
+            hsp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sweep(self, n=1):
+        hsp_sweep(self.h, n)
+
+    def sync(self):
+        hsp_sync(self.h)
+
+    def draws(self, first=0, count=None):
+        if count is None:
+            _, _, n = hsp_draws(self.h, 0, 0, self.p)
+            count = n - first
+        return hsp_draws(self.h, first, count, self.p, self.record_lambda)
+
+    def state(self):
+        return hsp_get_state(self.h, self.p)
+
+    def set_state(self, beta, lam_m2, nu_m1, tau_m2, xi_m1, sweep):
+        hsp_set_state(self.h, beta, lam_m2, nu_m1, tau_m2, xi_m1, sweep)
+
+    def step(self, which):
+        hsp_step(self.h, which)
+
+    def debug(self):
+        return hsp_get_debug(self.h, self.N, self.p)
+
+    def gram(self):
+        return hsp_get_gram(self.h, self.p)
+
+    def counters(self):
+        return hsp_get_counters(self.h)
+
+    def set_timing(self, enable):
+        hsp_set_timing(self.h, enable)
+
+    def timing(self):
+        return hsp_get_timing(self.h)
