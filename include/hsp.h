@@ -171,6 +171,15 @@ hsp_status hsp_get_counters(hsp_state* s, uint64_t* lambda_clamps, uint32_t* max
 hsp_status hsp_set_timing(hsp_state* s, int32_t enable);
 hsp_status hsp_get_timing(hsp_state* s, double* zpass_ms, double* sweep_ms, int64_t* n_sweeps);
 
+/* Diagnostics: when enabled, every launch of the sweep kernel stores, per
+ * block of its p-side group, a timestamp at the start (slot 0), after each
+ * group barrier (slots 1..), and when the z pass is seen complete (last slot).
+ * hsp_get_phase_trace copies group_blocks x slots uint64 values of the last
+ * launch; ticks_per_us converts them.  Enabling drops the captured graph. */
+hsp_status hsp_set_phase_trace(hsp_state* s, int32_t enable);
+hsp_status hsp_get_phase_trace(hsp_state* s, uint64_t* out, int64_t* group_blocks, int64_t* slots,
+                               double* ticks_per_us);
+
 /* Philox4x32-10 on the device: out[4i..4i+3] = Philox(ctr[4i..4i+3], key =
  * seed).  ctr and out are host arrays of 4n words.  Test hook for the
  * generator's bit-exactness. */

@@ -20,7 +20,6 @@ thread_local std::string g_create_error;
 struct hsp_state {
     int device = 0;
     int num_cus = 0;
-    size_t max_lds = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hsp_options opt{};
@@ -29,22 +28,23 @@ struct hsp_state {
     uint8_t* y = nullptr;
     Ctrl* ctrl = nullptr;
     double *beta = nullptr, *lam = nullptr, *nu = nullptr, *tau = nullptr, *xi = nullptr;
-    double *b = nullptr, *G = nullptr, *A = nullptr, *Ud = nullptr, *vec = nullptr;
-    double* partial = nullptr;
+    double *b = nullptr, *G = nullptr, *Gp = nullptr, *A = nullptr, *Linv = nullptr, *Dinv = nullptr;
+    double *vec = nullptr, *partial = nullptr, *gpartial = nullptr;
+    uint32_t* zgrp_count = nullptr;
     float* beta32 = nullptr;
     float* zdbg = nullptr;
     int32_t* adbg = nullptr;
     double *ring_beta = nullptr, *ring_tau = nullptr, *ring_lam = nullptr;
-    ZPassPlan plan{};
+    SweepPlan plan{};
+    uint64_t timeout_ticks = 0;
     uint64_t sweeps_done = 0;  // host mirror of ctrl->sweep
     uint64_t draw_base = 0;    // host mirror of ctrl->draw_base
     std::string err;
     bool poisoned = false;
-    hipGraphExec_t graph_full = nullptr;  // one whole sweep, recording
-    hipGraphExec_t graph_rest = nullptr;  // the sweep without the z pass
+    hipGraphExec_t graph = nullptr;  // one whole sweep (one kernel), recording
+    uint64_t* trace = nullptr;        // p-side phase timestamps (diagnostics)
     bool timing = false;
-    std::vector<hipEvent_t> ev;  // per timed sweep: z start, z end, sweep end
-    hipEvent_t ev_first = nullptr;
+    std::vector<hipEvent_t> ev;  // per timed sweep: start, end
     int64_t timed_sweeps = 0;
 };
 
@@ -79,72 +79,59 @@ hipError_t dalloc(T** p, size_t n) {
     return hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
 }
 
-PState pstate(hsp_state* s) {
-    PState p;
-    p.p = s->x.p;
-    p.beta = s->beta;
-    p.beta32 = s->beta32;
-    p.lam_m2 = s->lam;
-    p.nu_m1 = s->nu;
-    p.tau_m2 = s->tau;
-    p.xi_m1 = s->xi;
-    p.b = s->b;
-    p.G = s->G;
-    p.A = s->A;
-    p.Ud = s->Ud;
-    p.vec = s->vec;
-    p.ctrl = s->ctrl;
-    p.seed = s->opt.seed;
-    p.chain = s->opt.chain_id;
-    p.small_lds_ok = beta_small_fits(s->x.p, s->max_lds) ? 1 : 0;
-    return p;
-}
-
-ZPassArgs zargs(hsp_state* s) {
-    ZPassArgs a;
+SweepArgs sweep_args(hsp_state* s, uint32_t mode) {
+    SweepArgs a{};
     a.x = s->x;
     a.y = s->y;
     a.beta32 = s->beta32;
+    a.partial = s->partial;
+    a.gpartial = s->gpartial;
+    a.zgrp_count = s->zgrp_count;
+    a.zdbg = s->opt.debug_store_z ? s->zdbg : nullptr;
+    a.adbg = s->opt.debug_store_z ? s->adbg : nullptr;
+    a.beta = s->beta;
+    a.lam_m2 = s->lam;
+    a.nu_m1 = s->nu;
+    a.tau_m2 = s->tau;
+    a.xi_m1 = s->xi;
+    a.b = s->b;
+    a.G = s->G;
+    a.Gp = s->Gp;
+    a.A = s->A;
+    a.Linv = s->Linv;
+    a.Dinv = s->Dinv;
+    a.vec = s->vec;
+    a.ring_beta = s->ring_beta;
+    a.ring_tau = s->ring_tau;
+    a.ring_lam = s->ring_lam;
+    a.thin = (uint32_t)s->opt.thin;
+    a.capacity = (uint32_t)s->opt.max_draws;
     a.ctrl = s->ctrl;
     a.seed = s->opt.seed;
     a.chain = s->opt.chain_id;
-    a.partial = s->partial;
-    a.zdbg = s->opt.debug_store_z ? s->zdbg : nullptr;
-    a.adbg = s->opt.debug_store_z ? s->adbg : nullptr;
+    a.mode = mode;
+    a.timeout_ticks = s->timeout_ticks;
+    a.trace = s->trace;
     return a;
 }
 
-// The sweep's kernels after the z pass: b = X^T z, lambda^-2, tau^-2, beta,
-// nu^-1 and xi^-1, recording, sweep counter.
-hipError_t enqueue_rest(hsp_state* s, hipStream_t st, bool record) {
-    const PState ps = pstate(s);
-    hipError_t e;
-    if ((e = reduce_cols_launch(s->partial, s->plan.blocks, s->x.ld, s->x.p, s->b, st))) return e;
-    if ((e = lambda_launch(ps, st))) return e;
-    if ((e = tau_launch(ps, st))) return e;
-    if ((e = beta_launch(ps, st))) return e;
-    if ((e = nuxi_launch(ps, st))) return e;
-    if (record) {
-        if ((e = record_launch(ps, s->ring_beta, s->ring_tau, s->ring_lam, (uint32_t)s->opt.thin,
-                               (uint32_t)s->opt.max_draws, st)))
-            return e;
-    }
-    return advance_launch(s->ctrl, st);
-}
+constexpr uint32_t kModeSweep =
+    kModeZ | kModeLambda | kModeTau | kModeBeta | kModeNuXi | kModeRecord | kModeAdvance;
 
 hipError_t enqueue_sweep(hsp_state* s, hipStream_t st) {
-    hipError_t e = zpass_launch(zargs(s), s->plan, st);
-    if (e) return e;
-    return enqueue_rest(s, st, true);
+    return sweep_launch(sweep_args(s, kModeSweep), s->plan, st);
 }
 
-hipError_t capture(hsp_state* s, bool full, hipGraphExec_t* out) {
+hipError_t capture(hsp_state* s, hipGraphExec_t* out) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
     if (e) return e;
-    hipError_t e2 = full ? enqueue_sweep(s, s->stream) : enqueue_rest(s, s->stream, true);
+    hipError_t e2 = enqueue_sweep(s, s->stream);
     e = hipStreamEndCapture(s->stream, &g);
-    if (e2) { if (g) (void)hipGraphDestroy(g); return e2; }
+    if (e2) {
+        if (g) (void)hipGraphDestroy(g);
+        return e2;
+    }
     if (e) return e;
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -164,6 +151,8 @@ hsp_status check_device_flags(hsp_state* s) {
     if (c.err & kErrTnCap)
         return fail(s, HSP_ERANGE, "a truncated-normal row reached the proposal cap (non-finite X beta)");
     if (c.err & kErrNonFinite) return fail(s, HSP_ERANGE, "a draw of beta, lambda or tau was not finite");
+    if (c.err & kErrTimeout)
+        return fail(s, HSP_EHIP, "a bounded wait inside the sweep kernel timed out");
     return HSP_OK;
 }
 
@@ -175,13 +164,12 @@ hsp_status sync_state(hsp_state* s) {
 void free_state(hsp_state* s) {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
-    if (s->graph_full) (void)hipGraphExecDestroy(s->graph_full);
-    if (s->graph_rest) (void)hipGraphExecDestroy(s->graph_rest);
+    if (s->graph) (void)hipGraphExecDestroy(s->graph);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
-    if (s->ev_first) (void)hipEventDestroy(s->ev_first);
-    void* bufs[] = {s->Xbuf, s->y, s->ctrl, s->beta, s->lam, s->nu, s->tau, s->xi, s->b, s->G,
-                    s->A, s->Ud, s->vec, s->partial, s->beta32, s->zdbg, s->adbg, s->ring_beta,
-                    s->ring_tau, s->ring_lam};
+    void* bufs[] = {s->Xbuf, s->y, s->ctrl, s->beta, s->lam, s->nu, s->tau, s->xi, s->b, s->G, s->Gp,
+                    s->A, s->Linv, s->Dinv, s->vec, s->partial, s->beta32, s->zdbg, s->adbg,
+                    s->ring_beta, s->ring_tau, s->ring_lam, s->trace, s->gpartial,
+                    s->zgrp_count};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
@@ -207,6 +195,8 @@ hsp_status set_counters(hsp_state* s, uint64_t sweep) {
     HIP_TRY(hipMemcpy(&c, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
     c.sweep = (uint32_t)sweep;
     c.draw_base = (uint32_t)sweep;
+    c.bar_count = c.bar_epoch = 0;
+    c.z_count = c.z_epoch = 0;
     HIP_TRY(hipMemcpy(s->ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice));
     s->sweeps_done = sweep;
     s->draw_base = sweep;
@@ -217,13 +207,11 @@ hsp_status create_impl(hsp_state* s, const float* X, const uint8_t* y, int64_t N
     HIP_TRY(hipGetDevice(&s->device));
     HIP_TRY(hipDeviceGetAttribute(&s->num_cus, hipDeviceAttributeMultiprocessorCount, s->device));
     {
-        int lds = 0;
-        HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device));
-        s->max_lds = (size_t)lds;
-        if (pside_prepare(s->max_lds) != hipSuccess) {
-            (void)hipGetLastError();
-            s->max_lds = 65536;
-        }
+        // every wait inside the sweep kernel gives up after 2 seconds
+        int khz = 0;
+        HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device));
+        if (khz <= 0) khz = 100000;
+        s->timeout_ticks = (uint64_t)khz * 1000ull * 2ull;
     }
     if (s->opt.hip_stream) {
         s->stream = static_cast<hipStream_t>(s->opt.hip_stream);
@@ -280,24 +268,37 @@ hsp_status create_impl(hsp_state* s, const float* X, const uint8_t* y, int64_t N
     HIP_TRY(dalloc(&s->xi, 1));
     HIP_TRY(dalloc(&s->b, p));
     HIP_TRY(dalloc(&s->G, (size_t)p * p));
-    HIP_TRY(dalloc(&s->A, (size_t)p * p));
-    const size_t nt = ((size_t)p + 63) / 64;
-    HIP_TRY(dalloc(&s->Ud, nt * 64 * 64));
-    HIP_TRY(dalloc(&s->vec, 4 * (size_t)p));
-    HIP_TRY(hipMemsetAsync(s->A, 0, (size_t)p * p * sizeof(double), s->stream));
+    const size_t P = ((size_t)p + kTile - 1) / kTile * kTile;
+    if (p > kSmallP) {
+        HIP_TRY(dalloc(&s->Gp, P * P));
+        HIP_TRY(dalloc(&s->A, P * P));
+        HIP_TRY(dalloc(&s->Linv, P * P));
+        HIP_TRY(dalloc(&s->Dinv, P * kTile));
+        HIP_TRY(hipMemsetAsync(s->A, 0, P * P * sizeof(double), s->stream));
+        HIP_TRY(hipMemsetAsync(s->Linv, 0, P * P * sizeof(double), s->stream));
+    }
+    HIP_TRY(dalloc(&s->vec, 2 * (size_t)p + 8));
 
     // G = X^T X
     {
         double* work = nullptr;
         HIP_TRY(dalloc(&work, gram_work_doubles(s->x, s->num_cus)));
         hipError_t e = gram_launch(s->x, s->G, work, s->num_cus, s->stream);
+        if (!e && s->Gp) e = pad_gram_launch(s->G, (uint32_t)p, (uint32_t)P, s->Gp, s->stream);
         if (!e) e = hipStreamSynchronize(s->stream);
         (void)hipFree(work);
         HIP_TRY(e);
     }
 
-    s->plan = zpass_plan(s->x, s->num_cus);
-    HIP_TRY(dalloc(&s->partial, (size_t)s->plan.blocks * ld));
+    HIP_TRY(sweep_plan(s->x, s->num_cus, &s->plan));
+    HIP_TRY(dalloc(&s->partial, (size_t)s->plan.gz * ld));
+    {
+        const size_t ng = (s->plan.gz + kZGroup - 1) / kZGroup;
+        HIP_TRY(dalloc(&s->gpartial, ng * ld));
+        HIP_TRY(dalloc(&s->zgrp_count, ng));
+        HIP_TRY(hipMemsetAsync(s->zgrp_count, 0, ng * sizeof(uint32_t), s->stream));
+    }
+
     if (s->opt.debug_store_z) {
         HIP_TRY(dalloc(&s->zdbg, (size_t)N));
         HIP_TRY(dalloc(&s->adbg, (size_t)N));
@@ -384,32 +385,22 @@ hsp_status hsp_sweep(hsp_state* s, int64_t n) {
     if (n < 0) return fail(s, HSP_EINVAL, "n_iter must be >= 0");
     if (s->sweeps_done + (uint64_t)n >= (uint64_t(1) << 32) - 1)
         return fail(s, HSP_EINVAL, "the sweep counter would exceed 2^32");
-    if (s->timing) {
-        if (!s->graph_rest && s->opt.use_graph) {
-            hipError_t e = capture(s, false, &s->graph_rest);
-            if (e) return fail_hip(s, "graph capture", e);
-        }
-        for (int64_t i = 0; i < n; ++i) {
-            hipEvent_t e3[3];
-            for (auto& e : e3) HIP_TRY(hipEventCreate(&e));
-            for (auto& e : e3) s->ev.push_back(e);
-            HIP_TRY(hipEventRecord(e3[0], s->stream));
-            HIP_TRY(zpass_launch(zargs(s), s->plan, s->stream));
-            HIP_TRY(hipEventRecord(e3[1], s->stream));
-            if (s->graph_rest) HIP_TRY(hipGraphLaunch(s->graph_rest, s->stream));
-            else HIP_TRY(enqueue_rest(s, s->stream, true));
-            HIP_TRY(hipEventRecord(e3[2], s->stream));
-        }
-        s->timed_sweeps += n;
-    } else if (s->opt.use_graph) {
-        if (!s->graph_full) {
-            hipError_t e = capture(s, true, &s->graph_full);
-            if (e) return fail_hip(s, "graph capture", e);
-        }
-        for (int64_t i = 0; i < n; ++i) HIP_TRY(hipGraphLaunch(s->graph_full, s->stream));
-    } else {
-        for (int64_t i = 0; i < n; ++i) HIP_TRY(enqueue_sweep(s, s->stream));
+    if (s->opt.use_graph && !s->graph) {
+        hipError_t e = capture(s, &s->graph);
+        if (e) return fail_hip(s, "graph capture", e);
     }
+    for (int64_t i = 0; i < n; ++i) {
+        hipEvent_t e2[2] = {nullptr, nullptr};
+        if (s->timing) {
+            for (auto& e : e2) HIP_TRY(hipEventCreate(&e));
+            for (auto& e : e2) s->ev.push_back(e);
+            HIP_TRY(hipEventRecord(e2[0], s->stream));
+        }
+        if (s->graph) HIP_TRY(hipGraphLaunch(s->graph, s->stream));
+        else HIP_TRY(enqueue_sweep(s, s->stream));
+        if (s->timing) HIP_TRY(hipEventRecord(e2[1], s->stream));
+    }
+    if (s->timing) s->timed_sweeps += n;
     s->sweeps_done += (uint64_t)n;
     return HSP_OK;
 }
@@ -499,27 +490,26 @@ hsp_status hsp_set_state(hsp_state* s, const double* beta, const double* lam_m2,
 hsp_status hsp_step(hsp_state* s, uint32_t which) {
     if (!s) return HSP_EINVAL;
     if (s->poisoned) return HSP_EPOISONED;
-    const PState ps = pstate(s);
-    hipStream_t st = s->stream;
-    if (which & HSP_STEP_Z) {
-        HIP_TRY(zpass_launch(zargs(s), s->plan, st));
-        HIP_TRY(reduce_cols_launch(s->partial, s->plan.blocks, s->x.ld, s->x.p, s->b, st));
-    }
-    if (which & HSP_STEP_LAMBDA) HIP_TRY(lambda_launch(ps, st));
-    if (which & HSP_STEP_TAU) HIP_TRY(tau_launch(ps, st));
-    if (which & HSP_STEP_BETA) HIP_TRY(beta_launch(ps, st));
-    if (which & HSP_STEP_NUXI) HIP_TRY(nuxi_launch(ps, st));
+    uint32_t mode = 0;
+    if (which & HSP_STEP_Z) mode |= kModeZ;
+    if (which & HSP_STEP_LAMBDA) mode |= kModeLambda;
+    if (which & HSP_STEP_TAU) mode |= kModeTau;
+    if (which & HSP_STEP_BETA) mode |= kModeBeta;
+    if (which & HSP_STEP_NUXI) mode |= kModeNuXi;
+    if (which & HSP_STEP_ADVANCE) mode |= kModeAdvance;
+    HIP_TRY(sweep_launch(sweep_args(s, mode), s->plan, s->stream));
+    hsp_status st = sync_state(s);
+    if (st) return st;
     if (which & HSP_STEP_ADVANCE) {
-        HIP_TRY(advance_launch(s->ctrl, st));
+        // a stepped sweep records no draw: move the draw base with it
         s->sweeps_done += 1;
-        s->draw_base += 1;  // hsp_step never records a draw
+        s->draw_base += 1;
         Ctrl c;
-        HIP_TRY(hipStreamSynchronize(st));
         HIP_TRY(hipMemcpy(&c, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
         c.draw_base = (uint32_t)s->draw_base;
         HIP_TRY(hipMemcpy(s->ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice));
     }
-    return sync_state(s);
+    return HSP_OK;
 }
 
 hsp_status hsp_get_debug(hsp_state* s, float* z, int32_t* attempt, double* b) {
@@ -565,22 +555,55 @@ hsp_status hsp_set_timing(hsp_state* s, int32_t enable) {
 hsp_status hsp_get_timing(hsp_state* s, double* zpass_ms, double* sweep_ms, int64_t* n) {
     if (!s) return HSP_EINVAL;
     HIP_TRY(hipStreamSynchronize(s->stream));
-    double zsum = 0.0;
-    const size_t ns = s->ev.size() / 3;
+    double sum = 0.0;
+    const size_t ns = s->ev.size() / 2;
     for (size_t i = 0; i < ns; ++i) {
         float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, s->ev[3 * i], s->ev[3 * i + 1]));
-        zsum += ms;
+        HIP_TRY(hipEventElapsedTime(&ms, s->ev[2 * i], s->ev[2 * i + 1]));
+        sum += ms;
     }
     double total = 0.0;
     if (ns) {
         float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, s->ev[0], s->ev[3 * (ns - 1) + 2]));
+        HIP_TRY(hipEventElapsedTime(&ms, s->ev[0], s->ev[2 * ns - 1]));
         total = ms;
     }
-    if (zpass_ms) *zpass_ms = ns ? zsum / ns : 0.0;
+    // one kernel per sweep: the z pass and the p-side group share the launch
+    if (zpass_ms) *zpass_ms = ns ? sum / ns : 0.0;
     if (sweep_ms) *sweep_ms = ns ? total / ns : 0.0;
     if (n) *n = (int64_t)ns;
+    return HSP_OK;
+}
+
+hsp_status hsp_set_phase_trace(hsp_state* s, int32_t enable) {
+    if (!s) return HSP_EINVAL;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (s->graph) {
+        (void)hipGraphExecDestroy(s->graph);
+        s->graph = nullptr;
+    }
+    if (s->trace) {
+        (void)hipFree(s->trace);
+        s->trace = nullptr;
+    }
+    if (enable) {
+        HIP_TRY(dalloc(&s->trace, (size_t)kMaxGroup * kTraceSlots));
+        HIP_TRY(hipMemsetAsync(s->trace, 0, (size_t)kMaxGroup * kTraceSlots * 8, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+    return HSP_OK;
+}
+
+hsp_status hsp_get_phase_trace(hsp_state* s, uint64_t* out, int64_t* group_blocks, int64_t* slots,
+                               double* ticks_per_us) {
+    if (!s) return HSP_EINVAL;
+    if (!s->trace) return fail(s, HSP_EINVAL, "enable the trace with hsp_set_phase_trace first");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (out)
+        HIP_TRY(hipMemcpy(out, s->trace, (size_t)s->plan.gp * kTraceSlots * 8, hipMemcpyDeviceToHost));
+    if (group_blocks) *group_blocks = s->plan.gp;
+    if (slots) *slots = kTraceSlots;
+    if (ticks_per_us) *ticks_per_us = (double)s->timeout_ticks / 2e6;
     return HSP_OK;
 }
 

@@ -1,6 +1,8 @@
 // One-time work at creation: pack X into the library layout, validate the
-// inputs, and form G = X^T X in float64 (Section 5, beta step i).
+// inputs, and form G = X^T X in float64 (Section 5, beta step i).  Also the
+// device Philox test hook.
 #include "hsp_internal.hpp"
+#include "philox.hpp"
 
 namespace hsp {
 namespace {
@@ -126,7 +128,39 @@ void gram_geometry(const XLayout& x, int num_cus, uint32_t& nt, uint32_t& npairs
     rows_per_split = (uint32_t)rps;
 }
 
+__global__ void philox_test_kernel(uint64_t seed, const uint32_t* ctr, uint32_t n, uint32_t* out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Words4 w = philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3],
+                                   (uint32_t)seed, (uint32_t)(seed >> 32));
+    out[4 * i] = w.w0;
+    out[4 * i + 1] = w.w1;
+    out[4 * i + 2] = w.w2;
+    out[4 * i + 3] = w.w3;
+}
+
+__global__ void pad_gram_kernel(const double* __restrict__ G, uint32_t p, uint32_t P,
+                                double* __restrict__ Gp) {
+    const size_t n = (size_t)P * P;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t i = (uint32_t)(e / P), j = (uint32_t)(e % P);
+        Gp[e] = (i < p && j < p) ? G[(size_t)i * p + j] : (i == j ? 1.0 : 0.0);
+    }
+}
+
 }  // namespace
+
+hipError_t pad_gram_launch(const double* G, uint32_t p, uint32_t P, double* Gp, hipStream_t st) {
+    hipLaunchKernelGGL(pad_gram_kernel, dim3(1024), dim3(256), 0, st, G, p, P, Gp);
+    return hipGetLastError();
+}
+
+hipError_t philox_test_launch(uint64_t seed, const uint32_t* ctr, uint32_t n, uint32_t* out,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(philox_test_kernel, dim3((n + 255) / 256), dim3(256), 0, st, seed, ctr, n, out);
+    return hipGetLastError();
+}
 
 hipError_t pack_x_launch(const float* src, const XLayout& dst, hipStream_t st) {
     hipLaunchKernelGGL(pack_kernel, dim3(4096), dim3(256), 0, st, src, dst);

@@ -6,18 +6,31 @@
 namespace hsp {
 
 constexpr int kWave = 64;
-constexpr int kMaxP = 4096;          // largest p the register-tiled z pass supports
-constexpr uint32_t kMaxRounds = 2048; // 4096 truncated-normal proposals per row
+constexpr int kMaxP = 4096;            // largest p the register-tiled z pass supports
+constexpr uint32_t kMaxRounds = 2048;  // 4096 truncated-normal proposals per row
+constexpr int kThreads = 256;          // threads per block of the sweep kernel
+constexpr int kTile = 64;              // p-side tile edge
+constexpr int kSmallP = 128;           // p up to this runs the one-block p-side path
+constexpr int kMaxGroup = 32;          // most blocks of the p-side group
+constexpr int kZGroup = 16;            // z-pass blocks whose partials one block sums
+// LDS of one sweep-kernel block: two 64 x 65 float64 tiles (66,560 bytes).  The
+// same buffer holds the z pass's reduction segment and the packed Q of the
+// one-block path (p (p + 1) / 2 <= 8256 doubles for p <= 128).
+constexpr int kLdsDoubles = 2 * kTile * (kTile + 1);
 
 // Device control block, one per sampler state.
 struct Ctrl {
-    uint32_t sweep;          // completed sweeps; sweep k uses counter k = sweep + 1
-    uint32_t draw_base;      // value of sweep at creation or the last set_state
-    uint32_t err;            // kErr* bits
-    uint32_t max_attempts;   // most proposals any row needed
+    uint32_t sweep;             // completed sweeps; sweep k uses counter k = sweep + 1
+    uint32_t draw_base;         // value of sweep at creation or the last set_state
+    uint32_t err;               // kErr* bits
+    uint32_t max_attempts;      // most proposals any row needed
     unsigned long long clamps;  // lambda rates clamped to DBL_MIN
-    int32_t chol_info;       // first non-positive pivot (1-based), 0 if none
+    int32_t chol_info;          // first non-positive pivot (1-based), 0 if none
     uint32_t pad;
+    unsigned long long bar_count;  // arrivals at p-side group barriers (monotonic)
+    unsigned long long bar_epoch;  // bar_count when the current launch started
+    unsigned long long z_count;    // z-pass blocks finished (monotonic)
+    unsigned long long z_epoch;    // z_count when the current launch started
 };
 
 enum : uint32_t {
@@ -25,46 +38,89 @@ enum : uint32_t {
     kErrNotPD = 2u,      // non-positive pivot in the Cholesky factorisation
     kErrNonFinite = 4u,  // a p-sized draw became NaN or infinite
     kErrInput = 8u,      // invalid y or non-finite X at creation
+    kErrTimeout = 16u,   // a bounded wait inside the sweep kernel gave up
+};
+
+// Work selected for one launch of the sweep kernel.
+enum : uint32_t {
+    kModeZ = 1u,         // z pass and b = X^T z
+    kModeLambda = 2u,
+    kModeTau = 4u,
+    kModeBeta = 8u,
+    kModeNuXi = 16u,
+    kModeRecord = 32u,   // write the draw of this sweep into the ring
+    kModeAdvance = 64u,  // count the sweep as completed
 };
 
 // Layout of X in device memory: row-major, leading dimension ld elements,
 // ld a multiple of 16 bytes, padding columns zero.
 struct XLayout {
     const void* X;
-    int xtype;   // 0 float32, 1 bfloat16
+    int xtype;  // 0 float32, 1 bfloat16
     uint32_t N;
     uint32_t p;
     uint32_t ld;
 };
 
-// ---- launchers (each enqueues on the given stream) --------------------------
-struct ZPassArgs {
+// Everything one launch of the sweep kernel touches.
+struct SweepArgs {
     XLayout x;
     const uint8_t* y;
-    const float* beta32;
+    float* beta32;      // ld floats (padding zero): beta for the z pass
+    double* partial;    // gz x ld: per-block float64 partials of X^T z
+    double* gpartial;   // zgroups x ld: sums of kZGroup consecutive block partials
+    uint32_t* zgrp_count;  // zgroups arrival counters (zero between launches)
+    float* zdbg;        // optional: z of the last z pass (N)
+    int32_t* adbg;      // optional: accepted proposal | gauss bit (N)
+    double* beta;       // p
+    double* lam_m2;     // p
+    double* nu_m1;      // p
+    double* tau_m2;     // 1
+    double* xi_m1;      // 1
+    double* b;          // p: X^T z of the current sweep
+    const double* G;    // p x p Gram
+    const double* Gp;   // tile path: P x P, G with an identity block on the padding
+    double* A;          // tile path, P x P: U (P = p rounded up to 64)
+    double* Linv;       // tile path, P x P: lower triangle holds L^-1 = U^-T
+    double* Dinv;       // ceil(p/64) x 64 x 64: inverses of U's diagonal blocks
+    double* vec;        // 2 p scratch
+    double* ring_beta;  // capacity x p
+    double* ring_tau;   // capacity
+    double* ring_lam;   // capacity x p or null
+    uint32_t thin;
+    uint32_t capacity;
     Ctrl* ctrl;
     uint64_t seed;
     uint32_t chain;
-    double* partial;   // grid rows x ld, per-block partial sums of X^T z
-    float* zdbg;       // optional
-    int32_t* adbg;     // optional
+    uint32_t mode;           // kMode* bits
+    uint32_t gp;             // blocks of the p-side group (first in the grid)
+    uint32_t gz;             // z-pass blocks (after the group)
+    uint32_t zgroups;        // ceil(gz / kZGroup)
+    uint64_t timeout_ticks;  // bound of every wait, in s_memrealtime ticks
+    uint64_t* trace;         // optional: kTraceSlots timestamps per group block
 };
-struct ZPassPlan {
-    int blocks;    // grid size
-    int rows_per_wave_tile;
-    int chunks;
-};
-ZPassPlan zpass_plan(const XLayout& x, int num_cus);
-hipError_t zpass_launch(const ZPassArgs& a, const ZPassPlan& plan, hipStream_t st);
 
-// b[j] = sum over rows r < nrows of partial[r * ld + j], j < p, fixed order.
-hipError_t reduce_cols_launch(const double* partial, int nrows, uint32_t ld, uint32_t p,
-                              double* b, hipStream_t st);
+constexpr int kTraceSlots = 128;
+
+struct SweepPlan {
+    uint32_t gp;
+    uint32_t gz;
+    int chunks;    // 16-byte vectors per lane per row
+    int rows;      // rows per wave tile
+    int capacity;  // resident blocks of the chosen kernel on the device
+};
+
+// Plan a launch for X's shape; num_cus from the device.
+hipError_t sweep_plan(const XLayout& x, int num_cus, SweepPlan* plan);
+// Enqueue one launch of the sweep kernel.
+hipError_t sweep_launch(const SweepArgs& a, const SweepPlan& plan, hipStream_t st);
 
 // G = X^T X (p x p float64, leading dimension p); work must hold
 // gram_work_doubles(x) doubles.
 size_t gram_work_doubles(const XLayout& x, int num_cus);
 hipError_t gram_launch(const XLayout& x, double* G, double* work, int num_cus, hipStream_t st);
+// Gp (P x P) = G with an identity block beyond p, zeros elsewhere.
+hipError_t pad_gram_launch(const double* G, uint32_t p, uint32_t P, double* Gp, hipStream_t st);
 
 // Input validation: sets kErrInput in ctrl if a y is not 0/1 or an X entry is
 // not finite.
@@ -74,39 +130,6 @@ hipError_t validate_launch(const XLayout& x, const uint8_t* y, Ctrl* ctrl, hipSt
 // library layout.
 hipError_t pack_x_launch(const float* src, const XLayout& dst, hipStream_t st);
 
-// p-side state on the device.
-struct PState {
-    uint32_t p;
-    double* beta;      // p
-    float* beta32;     // ld (padding zero)
-    double* lam_m2;    // p
-    double* nu_m1;     // p
-    double* tau_m2;    // 1
-    double* xi_m1;     // 1
-    double* b;         // p: X^T z of the current sweep
-    const double* G;   // p x p
-    double* A;         // p x p workspace: Q, then the off-diagonal blocks of its
-                       // upper Cholesky factor
-    double* Ud;        // ceil(p/64) x 64 x 64: factors of the diagonal blocks
-    double* vec;       // 4 p workspace (s / v / w / mu)
-    Ctrl* ctrl;
-    uint64_t seed;
-    uint32_t chain;
-    int small_lds_ok;  // the one-block LDS beta kernel fits (p <= 128)
-};
-
-// Whether the one-block beta kernel fits p on a device with max_lds bytes of
-// LDS per block; pside_prepare raises that kernel's dynamic LDS limit.
-bool beta_small_fits(uint32_t p, size_t max_lds);
-hipError_t pside_prepare(size_t max_lds);
-
-hipError_t lambda_launch(const PState& s, hipStream_t st);
-hipError_t tau_launch(const PState& s, hipStream_t st);
-hipError_t beta_launch(const PState& s, hipStream_t st);   // Q, Cholesky, solves, beta
-hipError_t nuxi_launch(const PState& s, hipStream_t st);
-hipError_t record_launch(const PState& s, double* ring_beta, double* ring_tau,
-                         double* ring_lam, uint32_t thin, uint32_t capacity, hipStream_t st);
-hipError_t advance_launch(Ctrl* ctrl, hipStream_t st);
 hipError_t philox_test_launch(uint64_t seed, const uint32_t* ctr, uint32_t n, uint32_t* out,
                               hipStream_t st);
 

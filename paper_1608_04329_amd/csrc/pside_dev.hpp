@@ -1,0 +1,816 @@
+// The p-side role of the sweep kernel: the conditionals of Eq. (12) other
+// than z, in float64, computed by a group of gp blocks that run next to the
+// z-pass blocks of the same launch.
+//
+//   lambda_j^-2 ~ Exp(nu_j^-1 + tau^-2 beta_j^2 / 2)
+//   tau^-2      ~ Gamma((p+1)/2, rate xi^-1 + sum_j lambda_j^-2 beta_j^2 / 2)
+//   nu_j^-1     ~ Exp(1 + lambda_j^-2),   xi^-1 ~ Exp(1 + tau^-2)
+//   beta        ~ N(Q^-1 X^T z, Q^-1),  Q = X^T X + tau^-2 Lambda^-2
+// (rate parameterisation, Eq. 11; tau^-2 is the Gamma draw of Section 5's
+// sampling step, so tau^2 is inverse-gamma).  lambda, tau, nu, xi and the
+// Cholesky factorisation of Q depend only on the previous sweep, so the group
+// runs them while the z pass streams X; beta waits for the z pass.
+//
+// beta for p <= 128 (one block): Q packed in LDS, Q = U^T U by a right-looking
+// Cholesky, then s ~ N(0, I), U v = s, U^T w = b, U mu = w, beta = mu + v
+// (Section 5, beta steps ii-viii).
+//
+// beta for p > 128 (gp blocks, 64 x 64 tiles): a right-looking blocked
+// Cholesky that applies the same row operations to an identity block, so it
+// produces U and L^-1 = U^-T together (the factorisation of [Q | I]).  Then
+//   y = L^-1 b + s,   beta = L^-T y = U^-1 U^-T b + U^-1 s,
+// which is mean Q^-1 b plus noise with covariance U^-1 U^-T = Q^-1: the same
+// draw as the substitutions, as two parallel triangular products that run
+// after the z pass.
+//
+// Group barriers use a monotonic device counter; every wait is bounded in
+// time and sets kErrTimeout instead of hanging.
+#pragma once
+#include <float.h>
+
+#include "hsp_internal.hpp"
+#include "philox.hpp"
+
+namespace hsp {
+
+// ---- bounded waits and group barriers ---------------------------------------------
+struct Group {
+    uint64_t* trace;           // this block's timestamp slots, or null
+    Ctrl* ctrl;
+    unsigned long long base;   // bar_count when this launch started
+    unsigned long long zbase;  // z_count when this launch started
+    uint32_t size;
+    uint32_t n;                // barriers passed
+    uint64_t timeout;
+};
+
+// Block-uniform read of the failure flags that stop the group's work.
+__device__ __forceinline__ bool group_failed(const Group& g, double* lds_flag) {
+    __syncthreads();
+    if (threadIdx.x == 0)
+        lds_flag[0] = (__hip_atomic_load(&g.ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                       (kErrNotPD | kErrTimeout)) ? 1.0 : 0.0;
+    __syncthreads();
+    const bool f = lds_flag[0] != 0.0;
+    __syncthreads();
+    return f;
+}
+
+// Thread 0 only: wait until *ctr >= target, or give up after the timeout.
+__device__ __forceinline__ void wait_count(unsigned long long* ctr, unsigned long long target,
+                                        Ctrl* ctrl, uint64_t timeout) {
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout)
+            break;
+        if (wall_clock64() - t0 > timeout) {
+            atomicOr(&ctrl->err, kErrTimeout);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+__device__ __forceinline__ void group_sync(Group& g) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0 && g.size > 1) {
+        atomicAdd(&g.ctrl->bar_count, 1ull);
+        wait_count(&g.ctrl->bar_count, g.base + (unsigned long long)(g.n + 1) * g.size, g.ctrl,
+                   g.timeout);
+        __threadfence();
+    } else if (threadIdx.x == 0) {
+        atomicAdd(&g.ctrl->bar_count, 1ull);
+    }
+    g.n++;
+    if (g.trace && threadIdx.x == 0 && g.n < kTraceSlots - 1) g.trace[g.n] = wall_clock64();
+    __syncthreads();
+}
+
+// Block-wide float64 sum in a fixed order (identical result in every block).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kThreads / kWave; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+__device__ __forceinline__ uint32_t record_slot(const SweepArgs a, uint32_t k, bool* keep) {
+    const uint32_t since = k - a.ctrl->draw_base;
+    *keep = (a.mode & kModeRecord) && since % a.thin == 0;
+    return *keep ? (since / a.thin - 1u) % a.capacity : 0u;
+}
+
+// ---- lambda^-2 and tau^-2 (every block of the group computes them) ---------------
+// Returns tau^-2 (new if kModeTau).  Block `writer` stores lambda^-2 and tau^-2.
+__device__ double hyper_lambda_tau(const SweepArgs a, uint32_t k, bool writer, double* red) {
+    const uint32_t p = a.x.p;
+    const double tau_old = *a.tau_m2;
+    double acc = 0.0;
+    uint32_t clamps = 0;
+    bool bad = false;
+    for (uint32_t j = threadIdx.x; j < p; j += kThreads) {
+        const double bj = a.beta[j];
+        double lam;
+        if (a.mode & kModeLambda) {
+            double rate = a.nu_m1[j] + tau_old * bj * bj / 2.0;
+            if (!(rate >= DBL_MIN)) {
+                rate = DBL_MIN;
+                ++clamps;
+            }
+            const Words4 w = draw_words(a.seed, j, k, kTagLambda, 0, a.chain);
+            lam = -log(u01d(w.w0)) / rate;
+            if (!isfinite(lam)) bad = true;
+            if (writer) a.lam_m2[j] = lam;
+        } else {
+            lam = a.lam_m2[j];
+        }
+        acc += lam * bj * bj;
+    }
+    if (writer) {
+        if (clamps) atomicAdd(&a.ctrl->clamps, (unsigned long long)clamps);
+        if (bad) atomicOr(&a.ctrl->err, kErrNonFinite);
+    }
+    if (!(a.mode & kModeTau)) return tau_old;
+    const double sum = block_sum(acc, red);
+    // Cheng's GB: proposal m = 64 * round + lane, uniforms of Philox round m/2
+    // (words 0-1 for even m, 2-3 for odd m); the lowest accepted m wins, which
+    // is the first acceptance of the sequential algorithm.  (Section 5 uses 32
+    // threads and a serial scan for the same purpose.)
+    if (threadIdx.x < kWave) {
+        const int lane = threadIdx.x;
+        const double rate = *a.xi_m1 + sum / 2.0;
+        const double sh = ((double)p + 1.0) / 2.0;
+        const double A = 1.0 / sqrt(2.0 * sh - 1.0);
+        const double B = sh - log(4.0);
+        const double C = sh + 1.0 / A;
+        const double D = 1.0 + log(4.5);
+        double g = __builtin_nan("");
+        for (uint32_t round = 0; round < (1u << 16); ++round) {
+            const uint32_t m = round * kWave + lane;
+            const Words4 w = draw_words(a.seed, 0, k, kTagTau, m >> 1, a.chain);
+            const double u1 = u01d((m & 1u) ? w.w2 : w.w0);
+            const double u2 = u01d((m & 1u) ? w.w3 : w.w1);
+            const double V = A * log(u1 / (1.0 - u1));
+            const double X = sh * exp(V);
+            const double Z = u1 * u1 * u2;
+            const double R = B + C * V - X;
+            const bool ok = (R + D - 4.5 * Z >= 0.0) || (R >= log(Z));
+            const unsigned long long mask = __ballot(ok);
+            if (mask) {
+                g = __shfl(X, (int)(__ffsll((long long)mask) - 1));
+                break;
+            }
+        }
+        if (lane == 0) red[8] = g / rate;
+    }
+    __syncthreads();
+    const double tau = red[8];
+    // the other blocks may still be reading the old value: the new one goes to
+    // a scratch slot and is published when the launch closes
+    if (writer && threadIdx.x == 0) {
+        a.vec[2 * p] = tau;
+        if (!isfinite(tau) || !(tau > 0.0)) atomicOr(&a.ctrl->err, kErrNonFinite);
+    }
+    __syncthreads();
+    return tau;
+}
+
+// tau^-2 of this sweep: the scratch slot if it was drawn in this launch.
+__device__ __forceinline__ double current_tau(const SweepArgs a) {
+    // written by block 0 of the group in this launch: read past the scalar cache
+    return (a.mode & kModeTau)
+               ? __hip_atomic_load(a.vec + 2 * a.x.p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+               : *a.tau_m2;
+}
+
+// nu^-1 and xi^-1 from the (new) lambda^-2 and tau^-2 in memory.
+__device__ void hyper_nu_xi(const SweepArgs a, uint32_t k) {
+    const uint32_t p = a.x.p;
+    for (uint32_t j = threadIdx.x; j < p; j += kThreads) {
+        const Words4 w = draw_words(a.seed, j, k, kTagNu, 0, a.chain);
+        a.nu_m1[j] = -log(u01d(w.w0)) / (1.0 + a.lam_m2[j]);
+    }
+    if (threadIdx.x == 0) {
+        const Words4 w = draw_words(a.seed, 0, k, kTagXi, 0, a.chain);
+        *a.xi_m1 = -log(u01d(w.w0)) / (1.0 + current_tau(a));
+    }
+}
+
+// b = sum of the z-pass groups' partial rows, columns [c0, c1) by this block,
+// 16 columns x 16 row groups at a time, in a fixed order.
+__device__ void reduce_b_cols(const SweepArgs a, uint32_t c0, uint32_t c1, double* red) {
+    const int tc = threadIdx.x & 15, tr = threadIdx.x >> 4;
+    for (uint32_t cb = c0; cb < c1; cb += 16) {
+        const uint32_t col = cb + tc;
+        double s = 0.0;
+        if (col < c1)
+            for (uint32_t r = tr; r < a.zgroups; r += 16) s += a.gpartial[(size_t)r * a.x.ld + col];
+        red[tr * 17 + tc] = s;
+        __syncthreads();
+        if (tr == 0 && col < c1) {
+            double t = 0.0;
+            for (int i = 0; i < 16; ++i) t += red[i * 17 + tc];
+            a.b[col] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- one-block path, p <= 128 ----------------------------------------------------
+__device__ __forceinline__ uint32_t pk(uint32_t p, uint32_t i, uint32_t j) {
+    // packed upper triangle, row-major: row i starts at i p - i (i - 1) / 2
+    return i * p - (i * (i - 1u)) / 2u + (j - i);
+}
+
+__device__ double lane_elem(const double (&r)[2], uint32_t i) {
+    const double v0 = __shfl(r[0], (int)(i & 63u));
+    const double v1 = __shfl(r[1], (int)(i & 63u));
+    return i < 64u ? v0 : v1;
+}
+
+// One wave: U^T x = r (forward) or U x = r (backward), U packed in LDS;
+// lane l holds entries l and l + 64.
+__device__ void wave_solve(const double* U, uint32_t p, double (&r)[2], bool forward) {
+    const int lane = threadIdx.x & 63;
+    if (forward) {
+        for (uint32_t i = 0; i < p; ++i) {
+            const double xi = lane_elem(r, i) / U[pk(p, i, i)];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const uint32_t j = q * 64 + lane;
+                if (j == i) r[q] = xi;
+                else if (j > i && j < p) r[q] -= U[pk(p, i, j)] * xi;
+            }
+        }
+    } else {
+        for (int ii = (int)p - 1; ii >= 0; --ii) {
+            const uint32_t i = (uint32_t)ii;
+            const double xi = lane_elem(r, i) / U[pk(p, i, i)];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const uint32_t j = q * 64 + lane;
+                if (j == i) r[q] = xi;
+                else if (j < i) r[q] -= U[pk(p, j, i)] * xi;
+            }
+        }
+    }
+}
+
+__device__ void small_path(const SweepArgs a, Group& g, uint32_t k, double* lds) {
+    const uint32_t p = a.x.p;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double tau = hyper_lambda_tau(a, k, true, lds);
+    group_sync(g);  // lambda, tau in memory
+    if (a.mode & kModeNuXi) hyper_nu_xi(a, k);
+    bool bad = false;
+    if (a.mode & kModeBeta) {
+        double* U = lds;  // p (p + 1) / 2 doubles
+        for (uint32_t i = ty; i < p; i += 16)
+            for (uint32_t j = i + tx; j < p; j += 16)
+                U[pk(p, i, j)] = a.G[(size_t)i * p + j] + (i == j ? tau * a.lam_m2[i] : 0.0);
+        __syncthreads();
+        // right-looking, row scaling deferred: step c subtracts
+        // A[c][i] A[c][j] / A[c][c] from the trailing upper triangle
+        for (uint32_t c = 0; c < p; ++c) {
+            const double d = U[pk(p, c, c)];
+            if (!(d > 0.0)) {
+                bad = true;
+                break;
+            }
+            const double inv = 1.0 / d;
+            for (uint32_t i = c + 1 + ty; i < p; i += 16) {
+                const double f = U[pk(p, c, i)] * inv;
+                for (uint32_t j = i + tx; j < p; j += 16) U[pk(p, i, j)] -= f * U[pk(p, c, j)];
+            }
+            __syncthreads();
+        }
+        if (!bad) {
+            for (uint32_t i = ty; i < p; i += 16) {
+                const double rs = 1.0 / sqrt(U[pk(p, i, i)]);
+                for (uint32_t j = i + 1 + tx; j < p; j += 16) U[pk(p, i, j)] *= rs;
+            }
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < p; i += kThreads) U[pk(p, i, i)] = sqrt(U[pk(p, i, i)]);
+            __syncthreads();
+        } else if (threadIdx.x == 0) {
+            atomicOr(&a.ctrl->err, kErrNotPD);
+            for (uint32_t c = 0; c < p; ++c)
+                if (!(U[pk(p, c, c)] > 0.0)) {
+                    atomicCAS(&a.ctrl->chol_info, 0, (int)(c + 1));
+                    break;
+                }
+        }
+    }
+    if (a.mode & kModeZ) {
+        if (threadIdx.x == 0) wait_count(&a.ctrl->z_count, g.zbase + a.zgroups, a.ctrl, a.timeout_ticks);
+        __syncthreads();
+        __threadfence();
+        // one column per thread, summed over the group partial rows in order
+        for (uint32_t j = threadIdx.x; j < p; j += kThreads) {
+            double s = 0.0;
+            for (uint32_t r = 0; r < a.zgroups; ++r) s += a.gpartial[(size_t)r * a.x.ld + j];
+            a.b[j] = s;
+        }
+        __threadfence();
+        __syncthreads();
+    }
+    bool keep;
+    const uint32_t slot = record_slot(a, k, &keep);
+    if ((a.mode & kModeBeta) && !bad && threadIdx.x < kWave) {
+        const double* U = lds;
+        const int lane = threadIdx.x;
+        double v[2], w[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const uint32_t j = q * 64 + lane;
+            v[q] = 0.0;
+            w[q] = 0.0;
+            if (j < p) {
+                const Words4 wd = draw_words(a.seed, j, k, kTagBetaS, 0, a.chain);
+                v[q] = box_muller_d(u01d(wd.w0), u01d(wd.w1));
+                w[q] = a.b[j];
+            }
+        }
+        wave_solve(U, p, v, false);  // U v = s
+        wave_solve(U, p, w, true);   // U^T w = b
+        wave_solve(U, p, w, false);  // U mu = w
+        bool nonfinite = false;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const uint32_t j = q * 64 + lane;
+            if (j < p) {
+                const double bj = w[q] + v[q];
+                a.beta[j] = bj;
+                a.beta32[j] = (float)bj;
+                if (!isfinite(bj)) nonfinite = true;
+                if (keep) a.ring_beta[(size_t)slot * p + j] = bj;
+            }
+        }
+        if (__ballot(nonfinite) && lane == 0) atomicOr(&a.ctrl->err, kErrNonFinite);
+    }
+    if (keep) {
+        __syncthreads();
+        if (a.ring_lam)
+            for (uint32_t j = threadIdx.x; j < p; j += kThreads) a.ring_lam[(size_t)slot * p + j] = a.lam_m2[j];
+        if (threadIdx.x == 0) a.ring_tau[slot] = current_tau(a);
+    }
+}
+
+// ---- tile path, p > 128 ----------------------------------------------------------
+// The tile path works on P x P matrices, P = p rounded up to a multiple of 64,
+// leading dimension P: Gp holds G with an identity block on the padding, so
+// the factor, L^-1 and Q^-1 carry an identity block there too and no tile
+// ever needs a bounds check.
+typedef double Tile[kTile][kTile + 1];
+
+__device__ __forceinline__ uint32_t padded(uint32_t p) { return (p + kTile - 1) / kTile * kTile; }
+
+// T[r][c] = M[(r0 + r) P + c0 + c] (+ tau * lam on the diagonal of Q when
+// add_diag).  Thread t reads column t % 64 of rows t / 64 + 4q: every load
+// instruction of a wave is one contiguous 512-byte row segment, and all 16
+// loads of a thread are in flight together.
+__device__ __forceinline__ void load_tile(Tile& T, const double* M, uint32_t P, uint32_t r0,
+                                          uint32_t c0, bool add_diag, double tau,
+                                          const double* lam, uint32_t p) {
+    const int c = threadIdx.x & (kTile - 1), rb = threadIdx.x >> 6;
+    const double* src = M + (size_t)(r0 + rb) * P + c0 + c;
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = src[(size_t)(4 * q) * P];
+    if (add_diag) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const uint32_t gi = r0 + rb + 4 * q;
+            if (gi == c0 + c && gi < p) v[q] += tau * lam[gi];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) T[rb + 4 * q][c] = v[q];
+}
+
+// acc[t][u] = sum_q S[q][ty*4+t] * T[q][tx*4+u]  (a 64 x 64 x 64 product S^T T)
+__device__ __forceinline__ void gemm_tn(const Tile& S, const Tile& T, double (&acc)[4][4]) {
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll 4
+    for (int q = 0; q < kTile; ++q) {
+        double s[4], v[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            s[t] = S[q][ty * 4 + t];
+            v[t] = T[q][tx * 4 + t];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[t][u] = fma(s[t], v[u], acc[t][u]);
+    }
+}
+
+__device__ __forceinline__ void zero_acc(double (&acc)[4][4]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[t][u] = 0.0;
+}
+
+// M(r0.., c0..) = sign * acc + (old from src, with tau * lam on Q's diagonal if
+// add_diag).  Loads, arithmetic, then the 16 stores back to back.
+__device__ __forceinline__ void store_tile(double* M, uint32_t P, uint32_t r0, uint32_t c0,
+                                           const double (&acc)[4][4], double sign, const double* src,
+                                           bool add_diag, double tau, const double* lam, uint32_t p) {
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const size_t base = (size_t)(r0 + ty * 4) * P + c0 + tx * 4;
+    double out[4][4];
+    if (src) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) out[t][u] = src[base + (size_t)t * P + u];
+    } else {
+        zero_acc(out);
+    }
+    if (add_diag) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t gi = r0 + ty * 4 + t, gj = c0 + tx * 4 + u;
+                if (gi == gj && gi < p) out[t][u] += tau * lam[gi];
+            }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) out[t][u] = fma(sign, acc[t][u], out[t][u]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) M[base + (size_t)t * P + u] = out[t][u];
+}
+
+// The transpose of acc into M(c0.., r0..) (for symmetric results).
+__device__ __forceinline__ void store_tile_t(double* M, uint32_t P, uint32_t r0, uint32_t c0,
+                                             const double (&acc)[4][4]) {
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            M[(size_t)(c0 + tx * 4 + u) * P + r0 + ty * 4 + t] = acc[t][u];
+}
+
+// Inverse of the upper-triangular 64 x 64 U (in S) into T, by recursive
+// doubling: T starts as diag(1/U_ii); for b = 1, 2, ..., 32 every diagonal
+// 2b-block [U1 U12; 0 U2] gets W12 = -W1 (U12 W2).  U12 W2 is parked in the
+// (otherwise zero) lower-left b x b block and cleared at the end.  The inner
+// loops have compile-time length, so their LDS reads issue together.
+template <int LB>
+__device__ __forceinline__ void inverse_level(const Tile& S, Tile& T) {
+    constexpr int b = 1 << LB;
+    constexpr int n = (kTile / (2 * b)) * b * b;  // entries of all the b x b products
+    for (int e2 = threadIdx.x; e2 < n; e2 += kThreads) {
+        const int m = e2 >> (2 * LB), r = (e2 >> LB) & (b - 1), c = e2 & (b - 1);
+        const int o = 2 * b * m;
+        double x = 0.0;
+#pragma unroll
+        for (int q = 0; q < b; ++q) {
+            const double w = q <= c ? T[o + b + q][o + b + c] : 0.0;  // W2 is upper
+            x = fma(S[o + r][o + b + q], w, x);
+        }
+        T[o + b + r][o + c] = x;
+    }
+    __syncthreads();
+    for (int e2 = threadIdx.x; e2 < n; e2 += kThreads) {
+        const int m = e2 >> (2 * LB), r = (e2 >> LB) & (b - 1), c = e2 & (b - 1);
+        const int o = 2 * b * m;
+        double w = 0.0;
+#pragma unroll
+        for (int q = 0; q < b; ++q) {
+            const double v = q >= r ? T[o + r][o + q] : 0.0;  // W1 is upper
+            w = fma(v, T[o + b + q][o + c], w);
+        }
+        T[o + r][o + b + c] = -w;
+    }
+    __syncthreads();
+}
+
+// Factor a 64 x 64 diagonal block (upper part of S, zeros below; identity
+// beyond the matrix edge) into U (upper, in S) and its inverse (in T).
+//
+// Four row panels of 16.  For each, wave 0 eliminates the panel in registers:
+// lane j holds the panel's 16 entries of column j; at step c the pivot is
+// lane (r0 + c)'s entry c, row c is scaled by 1/sqrt(pivot), and the panel
+// rows below lose U[c][i] times it (U[c][i] read from lane r0 + i).  That is
+// both the 16 x 16 factorisation and the solve of the panel's columns to the
+// right.  Then every wave subtracts the panel's contribution from the
+// trailing block.  Eight barriers.  Returns false on a non-positive pivot
+// (uniformly: the flag goes through LDS).
+__device__ bool factor_diag(Tile& S, Tile& T) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double* flag = &T[kTile - 1][kTile];  // padding corner, not part of the tile
+#pragma unroll
+    for (int P = 0; P < 4; ++P) {
+        const int r0 = 16 * P;
+        if (wave == 0) {
+            double a[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) a[c] = S[r0 + c][lane];
+            bool ok = true;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const double d = __shfl(a[c], r0 + c);
+                ok = ok && (d > 0.0);
+                const double rs = 1.0 / sqrt(d);
+                a[c] = lane == r0 + c ? d * rs : a[c] * rs;
+#pragma unroll
+                for (int i = c + 1; i < 16; ++i) a[i] = fma(-__shfl(a[c], r0 + i), a[c], a[i]);
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) S[r0 + c][lane] = lane >= r0 + c ? a[c] : 0.0;
+            if (lane == 0) *flag = ok ? 0.0 : 1.0;
+        }
+        __syncthreads();
+        if (*flag != 0.0) return false;
+        // trailing update: S[i][j] -= sum_c S[r0+c][i] S[r0+c][j], r0+16 <= i <= j
+        constexpr int m0 = 0;
+        (void)m0;
+        const int m = 48 - r0;
+        for (int e = threadIdx.x; e < m * m; e += kThreads) {
+            const int i = r0 + 16 + e / m, j = r0 + 16 + e % m;
+            if (j >= i) {
+                double x = S[i][j];
+#pragma unroll
+                for (int c = 0; c < 16; ++c) x = fma(-S[r0 + c][i], S[r0 + c][j], x);
+                S[i][j] = x;
+            }
+        }
+        __syncthreads();
+    }
+    // T = U^-1
+    for (int e = threadIdx.x; e < kTile * kTile; e += kThreads) {
+        const int r = e / kTile, c = e % kTile;
+        T[r][c] = r == c ? 1.0 / S[r][r] : 0.0;
+    }
+    __syncthreads();
+    inverse_level<0>(S, T);
+    inverse_level<1>(S, T);
+    inverse_level<2>(S, T);
+    inverse_level<3>(S, T);
+    inverse_level<4>(S, T);
+    inverse_level<5>(S, T);
+    for (int e = threadIdx.x; e < kTile * kTile; e += kThreads) {
+        const int r = e / kTile, c = e % kTile;
+        if (c < r) T[r][c] = 0.0;
+    }
+    __syncthreads();
+    return true;
+}
+
+// Factor diagonal block kb: load it (from Gp + tau Lambda for kb = 0), factor,
+// store U_kk into A and its inverse into Dinv[kb].  Reports a failed pivot.
+__device__ void diag_block(const SweepArgs a, uint32_t kb, double tau, Tile& S, Tile& T) {
+    const uint32_t p = a.x.p, P = padded(p), k0 = kb * kTile;
+    load_tile(S, kb == 0 ? a.Gp : a.A, P, k0, k0, kb == 0, tau, a.lam_m2, p);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kTile * kTile; e += kThreads)
+        if (e % kTile < e / kTile) S[e / kTile][e % kTile] = 0.0;
+    __syncthreads();
+    if (factor_diag(S, T)) {
+        double* D = a.Dinv + (size_t)kb * kTile * kTile;
+        const int c = threadIdx.x & (kTile - 1), rb = threadIdx.x >> 6;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int r = rb + 4 * q;
+            a.A[(size_t)(k0 + r) * P + k0 + c] = S[r][c];
+            D[r * kTile + c] = T[r][c];
+        }
+    } else if (threadIdx.x == 0) {
+        atomicOr(&a.ctrl->err, kErrNotPD);
+        atomicCAS(&a.ctrl->chol_info, 0, (int)(k0 + 1));
+    }
+    __syncthreads();
+}
+
+// Decode update tile t of step kb: A-part tiles (i, j), kb < i <= j, come first,
+// then L^-1-part tiles (i, j), i > kb, j <= kb.
+__device__ __forceinline__ bool update_tile(uint32_t t, uint32_t kb, uint32_t nt, uint32_t* ib,
+                                            uint32_t* jb) {
+    const uint32_t m = nt - kb - 1, nA = m * (m + 1) / 2;
+    if (t < nA) {
+        uint32_t idx = t, r = 0;
+        while (idx >= m - r) {
+            idx -= m - r;
+            ++r;
+        }
+        *ib = kb + 1 + r;
+        *jb = *ib + idx;
+        return true;
+    }
+    const uint32_t t2 = t - nA;
+    *ib = kb + 1 + t2 / (kb + 1);
+    *jb = t2 % (kb + 1);
+    return false;
+}
+
+__device__ void tile_path(const SweepArgs a, Group& g, uint32_t rank, uint32_t k, double* lds) {
+    const uint32_t p = a.x.p, P = padded(p);
+    const uint32_t nt = P / kTile;
+    Tile& S = *reinterpret_cast<Tile*>(lds);
+    Tile& T = *reinterpret_cast<Tile*>(lds + kTile * (kTile + 1));
+    double* flag = lds + 2 * kTile * (kTile + 1) - 1;  // T's unused padding corner
+    const double tau = hyper_lambda_tau(a, k, rank == 0, lds);
+    group_sync(g);  // lambda^-2 and the new tau^-2 in memory
+    double* s_noise = a.vec + p;
+    if (rank == g.size - 1) {
+        if (a.mode & kModeNuXi) hyper_nu_xi(a, k);
+        if (a.mode & kModeBeta)
+            for (uint32_t i = threadIdx.x; i < p; i += kThreads) {
+                const Words4 w = draw_words(a.seed, i, k, kTagBetaS, 0, a.chain);
+                s_noise[i] = box_muller_d(u01d(w.w0), u01d(w.w1));
+            }
+    }
+
+    bool ok = true;
+    if (a.mode & kModeBeta) {
+        // Factorisation of [Q | I]: U in A (upper), L^-1 = U^-T in Linv (lower).
+        if (rank == 0) diag_block(a, 0, tau, S, T);
+        group_sync(g);
+        ok = !group_failed(g, flag);
+        for (uint32_t kb = 0; ok && kb < nt; ++kb) {
+            const uint32_t k0 = kb * kTile;
+            // row kb times D = U_kk^-1 (transposed): U_kj = D^T A_kj (j > kb),
+            // Linv_kj = D^T Linv_kj (j < kb), Linv_kk = D^T
+            for (uint32_t j = rank; j < nt; j += g.size) {
+                const double* Dk = a.Dinv + (size_t)kb * kTile * kTile;
+                {
+                    const int c = threadIdx.x & (kTile - 1), rb = threadIdx.x >> 6;
+                    double v[16];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) v[q] = Dk[(rb + 4 * q) * kTile + c];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) S[rb + 4 * q][c] = v[q];
+                }
+                const uint32_t j0 = j * kTile;
+                if (j == kb) {
+                    __syncthreads();
+                    const int c = threadIdx.x & (kTile - 1), rb = threadIdx.x >> 6;
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int r = rb + 4 * q;
+                        a.Linv[(size_t)(k0 + r) * P + k0 + c] = S[c][r];
+                    }
+                    __syncthreads();
+                    continue;
+                }
+                if (j > kb) load_tile(T, kb == 0 ? a.Gp : a.A, P, k0, j0, false, 0.0, nullptr, p);
+                else load_tile(T, a.Linv, P, k0, j0, false, 0.0, nullptr, p);
+                __syncthreads();
+                double acc[4][4];
+                zero_acc(acc);
+                gemm_tn(S, T, acc);
+                store_tile(j > kb ? a.A : a.Linv, P, k0, j0, acc, 1.0, nullptr, false, 0.0, nullptr, p);
+                __syncthreads();
+            }
+            group_sync(g);
+            if (kb + 1 == nt) break;
+            // trailing update A_ij -= U_ki^T U_kj (kb < i <= j) and
+            // Linv_ij -= U_ki^T Linv_kj (i > kb, j <= kb; Linv_i,kb starts at 0).
+            // Tile 0 is (kb+1, kb+1): block 0 updates it alone and factors it
+            // at once (look-ahead), the other blocks share the rest.
+            const uint32_t m = nt - kb - 1;
+            const uint32_t ntiles = m * (m + 1) / 2 + m * (kb + 1);
+            for (uint32_t t = rank == 0 ? 0u : rank; t < ntiles; t += g.size - 1) {
+                uint32_t ib, jb;
+                const bool apart = update_tile(t, kb, nt, &ib, &jb);
+                load_tile(S, a.A, P, k0, ib * kTile, false, 0.0, nullptr, p);
+                load_tile(T, apart ? a.A : a.Linv, P, k0, jb * kTile, false, 0.0, nullptr, p);
+                __syncthreads();
+                double acc[4][4];
+                zero_acc(acc);
+                gemm_tn(S, T, acc);
+                if (apart)
+                    store_tile(a.A, P, ib * kTile, jb * kTile, acc, -1.0, kb == 0 ? a.Gp : a.A,
+                               kb == 0 && ib == jb, tau, a.lam_m2, p);
+                else
+                    store_tile(a.Linv, P, ib * kTile, jb * kTile, acc, -1.0,
+                               jb == kb ? nullptr : a.Linv, false, 0.0, nullptr, p);
+                __syncthreads();
+                if (rank == 0) break;  // block 0 owns tile 0 only
+            }
+            if (rank == 0) diag_block(a, kb + 1, tau, S, T);
+            group_sync(g);
+            ok = !group_failed(g, flag);
+        }
+    }
+
+    if (a.mode & kModeZ) {
+        if (threadIdx.x == 0) wait_count(&a.ctrl->z_count, g.zbase + a.zgroups, a.ctrl, a.timeout_ticks);
+        if (g.trace && threadIdx.x == 0) g.trace[kTraceSlots - 1] = wall_clock64();
+        __syncthreads();
+        __threadfence();
+        const uint32_t per = ((p + g.size - 1) / g.size + 15) / 16 * 16;
+        const uint32_t c0 = rank * per, c1 = min(p, c0 + per);
+        if (c0 < c1) reduce_b_cols(a, c0, c1, lds);
+        group_sync(g);
+    }
+
+    if ((a.mode & kModeBeta) && ok) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        // y = L^-1 b + s: four rows per wave at a time, b from LDS
+        double* bl = lds;
+        for (uint32_t j = threadIdx.x; j < p; j += kThreads) bl[j] = a.b[j];
+        __syncthreads();
+        double* yv = a.vec;
+        for (uint32_t i0 = (rank * 4 + wave) * 4; i0 < p; i0 += g.size * 16) {
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            const uint32_t iend = min(i0 + 3, p - 1);  // row i sums j <= i
+#pragma unroll 4
+            for (uint32_t j = lane; j <= iend; j += 64) {
+                const double bj = bl[j];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t i = i0 + r;
+                    if (i < p && j <= i) acc[r] = fma(a.Linv[(size_t)i * P + j], bj, acc[r]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) acc[r] += __shfl_xor(acc[r], off);
+            if (lane < 4 && i0 + lane < p) {
+                double yi = acc[0];
+#pragma unroll
+                for (int r = 1; r < 4; ++r) yi = lane == r ? acc[r] : yi;
+                yv[i0 + lane] = yi + s_noise[i0 + lane];
+            }
+        }
+        group_sync(g);
+        // beta = L^-T y: 32 columns x 8 row groups per pass, y from LDS
+        double* yl = lds;
+        for (uint32_t j = threadIdx.x; j < p; j += kThreads) yl[j] = yv[j];
+        double* red = lds + P;
+        __syncthreads();
+        bool keep;
+        const uint32_t slot = record_slot(a, k, &keep);
+        const int tc = threadIdx.x & 31, tr = threadIdx.x >> 5;
+        bool nonfinite = false;
+        for (uint32_t cb = rank * 32; cb < p; cb += g.size * 32) {
+            const uint32_t col = cb + tc;
+            double acc = 0.0;
+#pragma unroll 4
+            for (uint32_t i = cb + tr; i < p; i += 8)
+                if (i >= col) acc = fma(a.Linv[(size_t)i * P + col], yl[i], acc);
+            red[tr * 33 + tc] = acc;
+            __syncthreads();
+            if (tr == 0 && col < p) {
+                double bi = 0.0;
+                for (int q = 0; q < 8; ++q) bi += red[q * 33 + tc];
+                a.beta[col] = bi;
+                a.beta32[col] = (float)bi;
+                if (!isfinite(bi)) nonfinite = true;
+                if (keep) {
+                    a.ring_beta[(size_t)slot * p + col] = bi;
+                    if (a.ring_lam) a.ring_lam[(size_t)slot * p + col] = a.lam_m2[col];
+                }
+            }
+            __syncthreads();
+        }
+        if (nonfinite) atomicOr(&a.ctrl->err, kErrNonFinite);
+        if (keep && rank == 0 && threadIdx.x == 0) a.ring_tau[slot] = current_tau(a);
+    }
+}
+
+// The whole p-side role of block `rank` of the group.
+__device__ __forceinline__ void pside_role(const SweepArgs a, uint32_t rank, uint32_t k, double* lds) {
+    Group g;
+    g.trace = a.trace ? a.trace + (size_t)rank * kTraceSlots : nullptr;
+    if (g.trace && threadIdx.x == 0) g.trace[0] = wall_clock64();
+    g.ctrl = a.ctrl;
+    g.base = a.ctrl->bar_epoch;
+    g.zbase = a.ctrl->z_epoch;
+    g.size = a.gp;
+    g.n = 0;
+    g.timeout = a.timeout_ticks;
+    if (a.x.p <= (uint32_t)kSmallP) small_path(a, g, k, lds);
+    else tile_path(a, g, rank, k, lds);
+    // the last barrier above was passed by every block of the group, and the
+    // z-pass blocks have all finished if they ran: close the launch
+    if (rank == 0) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            a.ctrl->bar_epoch = g.base + (unsigned long long)g.n * g.size;
+            if (a.mode & kModeZ) a.ctrl->z_epoch = g.zbase + a.zgroups;
+            if (a.mode & kModeTau) *a.tau_m2 = current_tau(a);
+            if (a.mode & kModeAdvance) a.ctrl->sweep = k;
+            __threadfence();
+        }
+    }
+}
+
+}  // namespace hsp

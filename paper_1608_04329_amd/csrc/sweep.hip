@@ -1,0 +1,87 @@
+// One Gibbs sweep as one kernel launch.
+//
+// The grid has two roles.  Blocks [0, gp) form the p-side group: lambda^-2,
+// tau^-2, nu^-1, xi^-1 and the Cholesky factorisation of Q need only the
+// previous sweep, so they run while blocks [gp, gp + gz) stream X through the
+// z pass (z | beta and the partial sums of X^T z).  The group then waits for
+// the z pass, reduces X^T z and draws beta.  This is the schedule of
+// Section 5 -- (i) z in parallel with lambda, then tau; (ii) beta with nu and
+// xi -- inside a single launch, so a sweep costs one graph node and the
+// p-side work hides under the bandwidth-bound pass over X.
+//
+// The group blocks come first in the grid: they are dispatched before any
+// z-pass block and stay resident, so their barriers only ever wait on
+// blocks that are running.  The z-pass blocks never wait on anything.
+#include <utility>
+
+#include "pside_dev.hpp"
+#include "zpass_dev.hpp"
+
+namespace hsp {
+namespace {
+
+template <int XT, int KC, int R>
+__global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
+    __shared__ double lds[kLdsDoubles];
+    const uint32_t k = a.ctrl->sweep + 1u;
+    if (blockIdx.x < a.gp) pside_role(a, blockIdx.x, k, lds);
+    else zpass_role<XT, KC, R>(a, blockIdx.x - a.gp, a.gz, k, lds);
+}
+
+constexpr int rows_for_chunks(int kc) { return kc <= 4 ? 8 : (kc <= 8 ? 4 : 2); }
+
+using KernelFn = void (*)(SweepArgs);
+
+template <int XT, int... KCs>
+KernelFn pick(int kc, std::integer_sequence<int, KCs...>) {
+    KernelFn f = nullptr;
+    ((kc == KCs + 1 ? (f = &sweep_kernel<XT, KCs + 1, rows_for_chunks(KCs + 1)>, 0) : 0), ...);
+    return f;
+}
+
+KernelFn kernel_for(int xtype, int chunks) {
+    if (xtype == 0) return pick<0>(chunks, std::make_integer_sequence<int, kMaxP / (kWave * 4)>{});
+    return pick<1>(chunks, std::make_integer_sequence<int, kMaxP / (kWave * 8)>{});
+}
+
+}  // namespace
+
+hipError_t sweep_plan(const XLayout& x, int num_cus, SweepPlan* plan) {
+    const int vec = x.xtype == 0 ? 4 : 8;
+    plan->chunks = (int)((x.ld + kWave * vec - 1) / (kWave * vec));
+    plan->rows = rows_for_chunks(plan->chunks);
+    KernelFn f = kernel_for(x.xtype, plan->chunks);
+    if (!f) return hipErrorInvalidValue;
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(f),
+                                                                kThreads, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    plan->capacity = per_cu * num_cus;
+    const uint32_t nt = (x.p + kTile - 1) / kTile;
+    uint32_t gp = x.p <= (uint32_t)kSmallP ? 1u : nt * (nt + 1) / 2;
+    if (gp > (uint32_t)kMaxGroup) gp = kMaxGroup;
+    if (gp > (uint32_t)plan->capacity / 4) gp = plan->capacity / 4 > 0 ? plan->capacity / 4 : 1;
+    plan->gp = gp;
+    const uint64_t tiles = (x.N + plan->rows - 1) / plan->rows;
+    uint64_t gz = (tiles + kWPB - 1) / kWPB;
+    const uint64_t room = (uint64_t)plan->capacity - gp;
+    if (gz > room) gz = room;
+    if (gz < 1) gz = 1;
+    plan->gz = (uint32_t)gz;
+    return hipSuccess;
+}
+
+hipError_t sweep_launch(const SweepArgs& a0, const SweepPlan& plan, hipStream_t st) {
+    KernelFn f = kernel_for(a0.x.xtype, plan.chunks);
+    if (!f) return hipErrorInvalidValue;
+    SweepArgs a = a0;
+    a.gp = plan.gp;
+    a.gz = (a.mode & kModeZ) ? plan.gz : 0u;
+    a.zgroups = (a.gz + kZGroup - 1) / kZGroup;
+    void* args[] = {&a};
+    return hipLaunchKernel(reinterpret_cast<const void*>(f), dim3(a.gp + a.gz), dim3(kThreads), args,
+                           0, st);
+}
+
+}  // namespace hsp

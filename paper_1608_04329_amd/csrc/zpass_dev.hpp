@@ -7,7 +7,7 @@
 // lane loads 16-byte vectors of every row (coalesced across the wave), the
 // wave reduces the R dot products, lanes 0..R-1 draw one truncated normal
 // each, and the same registers then feed x_i^T z_i.  X is read from HBM
-// exactly once; eta and z never touch memory.
+// exactly once per sweep; eta and z never touch memory.
 //
 // Truncated normal, divergence-free: with y* = 2y - 1 and mu* = y* eta the
 // draw is t ~ N(mu*, 1) restricted to t > 0 and z = y* t (the y* trick of
@@ -23,15 +23,14 @@
 //               of cancellation).
 // So lanes on different branches run the same instructions.  Proposal a of
 // row i uses Philox round a/2 (two proposals per call).
+#pragma once
 #include "hsp_internal.hpp"
 #include "philox.hpp"
 
 namespace hsp {
-namespace {
 
-constexpr int kWPB = 4;                 // waves per block
-constexpr int kThreads = kWPB * kWave;  // 256
-constexpr int kRedCols = 1024;          // columns per LDS reduction segment
+constexpr int kWPB = kThreads / kWave;  // waves per block
+constexpr int kRedCols = kLdsDoubles / kWPB;  // columns per LDS reduction segment
 
 template <int XT>
 struct XTraits;
@@ -72,18 +71,18 @@ __device__ __forceinline__ void tn_candidate(float mu, bool gauss, float theta, 
     acc = gauss ? (tg > 0.0f) : (ub < rho);
 }
 
+// The z-pass role of the sweep kernel: block zrank of nz z-pass blocks.
 template <int XT, int KC, int R>
-__global__ __launch_bounds__(kThreads) void zpass_kernel(ZPassArgs a) {
+__device__ __forceinline__ void zpass_role(const SweepArgs a, uint32_t zrank, uint32_t nz,
+                                           uint32_t ksweep, double* red) {
     constexpr int VEC = XTraits<XT>::VEC;
     constexpr int EB = XTraits<XT>::BYTES;
     constexpr int CW = kWave * VEC;  // columns covered by one wave-wide 16-byte load
-    __shared__ double red[kWPB * kRedCols];
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const uint32_t ld = a.x.ld;
     const uint32_t N = a.x.N;
-    const uint32_t ksweep = a.ctrl->sweep + 1u;
     const char* __restrict__ Xb = static_cast<const char*>(a.x.X);
     const size_t row_bytes = (size_t)ld * EB;
 
@@ -99,11 +98,11 @@ __global__ __launch_bounds__(kThreads) void zpass_kernel(ZPassArgs a) {
         }
 
     const uint32_t n_tiles = (N + R - 1) / R;
-    const uint32_t W = gridDim.x * kWPB;
+    const uint32_t W = nz * kWPB;
     uint32_t maxatt = 0;
     bool capped = false;
 
-    for (uint32_t t = blockIdx.x * kWPB + wave; t < n_tiles; t += W) {
+    for (uint32_t t = zrank * kWPB + wave; t < n_tiles; t += W) {
         const uint32_t row0 = t * R;
         uint4 xr[R][KC];
 #pragma unroll
@@ -220,82 +219,46 @@ __global__ __launch_bounds__(kThreads) void zpass_kernel(ZPassArgs a) {
             double v = red[c];
 #pragma unroll
             for (int w = 1; w < kWPB; ++w) v += red[w * kRedCols + c];
-            a.partial[(size_t)blockIdx.x * ld + seg + c] = v;
+            a.partial[(size_t)zrank * ld + seg + c] = v;
         }
         __syncthreads();
     }
-}
-
-__global__ __launch_bounds__(256) void reduce_cols_kernel(const double* __restrict__ partial,
-                                                          int nrows, uint32_t ld, uint32_t p,
-                                                          double* __restrict__ b) {
-    __shared__ double red[16][17];
-    const int tc = threadIdx.x & 15, tr = threadIdx.x >> 4;
-    const uint32_t col = blockIdx.x * 16 + tc;
-    double s = 0.0;
-    if (col < p)
-        for (int r = tr; r < nrows; r += 16) s += partial[(size_t)r * ld + col];
-    red[tr][tc] = s;
+    // This block's partial is complete.  The last of each group of kZGroup
+    // consecutive blocks to finish adds the group's partials in block order
+    // (deterministic) and publishes the group sum; the p-side waits for all
+    // groups.  Every thread's stores are made visible device-wide first.
+    __threadfence();
     __syncthreads();
-    if (tr == 0 && col < p) {
-        double t = 0.0;
-        for (int i = 0; i < 16; ++i) t += red[i][tc];
-        b[col] = t;
+    const uint32_t grp = zrank / kZGroup;
+    const uint32_t g0 = grp * kZGroup;
+    const uint32_t gsize = min((uint32_t)kZGroup, nz - g0);
+    if (threadIdx.x == 0) {
+        const uint32_t old = atomicAdd(&a.zgrp_count[grp], 1u);
+        red[0] = (old == gsize - 1) ? 1.0 : 0.0;
     }
-}
-
-template <int XT>
-constexpr int rows_for_chunks(int kc) {
-    return kc <= 4 ? 8 : (kc <= 8 ? 4 : 2);
-}
-
-template <int XT, int KC>
-hipError_t launch_kc(const ZPassArgs& a, int blocks, hipStream_t st) {
-    constexpr int R = rows_for_chunks<XT>(KC);
-    hipLaunchKernelGGL((zpass_kernel<XT, KC, R>), dim3(blocks), dim3(kThreads), 0, st, a);
-    return hipGetLastError();
-}
-
-template <int XT, int... KCs>
-hipError_t dispatch(const ZPassArgs& a, int kc, int blocks, hipStream_t st,
-                    std::integer_sequence<int, KCs...>) {
-    hipError_t e = hipErrorInvalidValue;
-    ((kc == KCs + 1 ? (e = launch_kc<XT, KCs + 1>(a, blocks, st), 0) : 0), ...);
-    return e;
-}
-
-}  // namespace
-
-ZPassPlan zpass_plan(const XLayout& x, int num_cus) {
-    const int vec = x.xtype == 0 ? 4 : 8;
-    const int cw = kWave * vec;
-    ZPassPlan plan;
-    plan.chunks = (int)((x.ld + cw - 1) / cw);
-    plan.rows_per_wave_tile = x.xtype == 0 ? rows_for_chunks<0>(plan.chunks)
-                                           : rows_for_chunks<1>(plan.chunks);
-    const uint64_t tiles = (x.N + plan.rows_per_wave_tile - 1) / plan.rows_per_wave_tile;
-    const uint64_t need = (tiles + kWPB - 1) / kWPB;
-    int per_cu = 2;
-    if (const char* env = getenv("HSP_ZPASS_BLOCKS_PER_CU")) per_cu = atoi(env) > 0 ? atoi(env) : 2;
-    const uint64_t cap = (uint64_t)num_cus * per_cu;
-    plan.blocks = (int)(need < cap ? need : cap);
-    if (plan.blocks < 1) plan.blocks = 1;
-    return plan;
-}
-
-hipError_t zpass_launch(const ZPassArgs& a, const ZPassPlan& plan, hipStream_t st) {
-    const int max_kc = a.x.xtype == 0 ? kMaxP / (kWave * 4) : kMaxP / (kWave * 8);
-    if (plan.chunks < 1 || plan.chunks > max_kc) return hipErrorInvalidValue;
-    if (a.x.xtype == 0)
-        return dispatch<0>(a, plan.chunks, plan.blocks, st, std::make_integer_sequence<int, 16>{});
-    return dispatch<1>(a, plan.chunks, plan.blocks, st, std::make_integer_sequence<int, 8>{});
-}
-
-hipError_t reduce_cols_launch(const double* partial, int nrows, uint32_t ld, uint32_t p,
-                              double* b, hipStream_t st) {
-    hipLaunchKernelGGL(reduce_cols_kernel, dim3((p + 15) / 16), dim3(256), 0, st, partial, nrows,
-                       ld, p, b);
-    return hipGetLastError();
+    __syncthreads();
+    const bool last = red[0] != 0.0;
+    __syncthreads();
+    if (last) {
+        __threadfence();
+        for (uint32_t c = threadIdx.x; c < ld; c += kThreads) {
+            double v[kZGroup];
+#pragma unroll
+            for (int r = 0; r < kZGroup; ++r)
+                v[r] = (uint32_t)r < gsize ? a.partial[(size_t)(g0 + r) * ld + c] : 0.0;
+            double s = v[0];
+#pragma unroll
+            for (int r = 1; r < kZGroup; ++r) s += v[r];
+            a.gpartial[(size_t)grp * ld + c] = s;
+        }
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            a.zgrp_count[grp] = 0u;  // every block of the group has arrived
+            __threadfence();
+            atomicAdd(&a.ctrl->z_count, 1ull);
+        }
+    }
 }
 
 }  // namespace hsp

@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "HSP_OK", -1: "HSP_EINVAL", -2: "HSP_ENOMEM", -3: "HSP_EHIP",
 EXPORTS = ["hsp_default_options", "hsp_max_p", "hsp_create", "hsp_sweep", "hsp_sync", "hsp_draws",
            "hsp_destroy", "hsp_last_error", "hsp_get_state", "hsp_set_state", "hsp_step",
            "hsp_get_debug", "hsp_get_gram", "hsp_get_counters", "hsp_set_timing",
-           "hsp_get_timing", "hsp_philox"]
+           "hsp_get_timing", "hsp_philox", "hsp_set_phase_trace", "hsp_get_phase_trace"]
 
 
 class hsp_options(C.Structure):
@@ -77,6 +77,9 @@ def load():
     L.hsp_get_timing.argtypes = [vp, C.POINTER(d), C.POINTER(d), C.POINTER(i64)]
     L.hsp_get_timing.restype = st
     L.hsp_philox.argtypes = [u64, vp, i64, vp]; L.hsp_philox.restype = st
+    L.hsp_set_phase_trace.argtypes = [vp, i32]; L.hsp_set_phase_trace.restype = st
+    L.hsp_get_phase_trace.argtypes = [vp, vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(d)]
+    L.hsp_get_phase_trace.restype = st
     _lib = L
     return L
 
@@ -186,6 +189,18 @@ def hsp_philox(seed, ctr):
     out = np.zeros_like(ctr)
     _check(load().hsp_philox(seed, _hp(ctr), ctr.shape[0], _hp(out)))
     return out
+
+
+def hsp_set_phase_trace(h, enable):
+    _check(load().hsp_set_phase_trace(h, int(enable)), h)
+
+
+def hsp_get_phase_trace(h):
+    gb, sl, tpu = C.c_int64(), C.c_int64(), C.c_double()
+    _check(load().hsp_get_phase_trace(h, None, C.byref(gb), C.byref(sl), C.byref(tpu)), h)
+    out = np.zeros((gb.value, sl.value), np.uint64)
+    _check(load().hsp_get_phase_trace(h, _hp(out), C.byref(gb), C.byref(sl), C.byref(tpu)), h)
+    return out, tpu.value
 
 
 # ---- convenience wrapper --------------------------------------------------------

@@ -1,0 +1,124 @@
+"""GPU: long chains and the full-size workload.
+
+* Long-chain parity: GPU chains and oracle chains with independent seeds must
+  agree on the posterior mean and variance of every beta_j within
+  4 sqrt(MCSE_gpu^2 + MCSE_oracle^2) (batch means, 20% burn-in), and the
+  sign of each nonzero beta_true must be recovered (Section 6.1).
+* Full size (N = 1,000,000, p = 1000, float32 X; the benchmark's launch): one
+  z step and X^T z compared with the oracle on every row, G on sampled
+  entries, and 50 whole sweeps checked for the sign invariant and finiteness.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import b_scale, need_gpu, z_scale
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    return need_gpu()
+
+
+def batch_se(x):
+    n = x.shape[0]
+    nb = int(math.sqrt(n))
+    m = n // nb
+    bm = x[: nb * m].reshape(nb, m, *x.shape[1:]).mean(1)
+    return bm.std(0, ddof=1) / math.sqrt(nb)
+
+
+def pooled(chains):
+    """Mean, variance and their batch-means standard errors over independent chains."""
+    mus, vs, se_m, se_v = [], [], [], []
+    for c in chains:
+        mus.append(c.mean(0))
+        se_m.append(batch_se(c))
+    mu = np.mean(mus, 0)
+    for c in chains:
+        sq = (c - mu) ** 2
+        vs.append(sq.mean(0))
+        se_v.append(batch_se(sq))
+    k = len(chains)
+    return (mu, np.sqrt(np.sum(np.square(se_m), 0)) / k, np.mean(vs, 0),
+            np.sqrt(np.sum(np.square(se_v), 0)) / k)
+
+
+@pytest.mark.parametrize("which", ["n1000_p10", "n4000_p130"])
+def test_long_chain_moments_agree_with_oracle(env, orc, which):
+    torch, hsp = env
+    if which == "n1000_p10":
+        d = synth.config1()
+        n, chains = 3000, 4
+    else:
+        beta, _ = synth.sparse_beta(130, 5, 17, -2.0, 2.0)
+        d = synth.probit_design(4000, 130, beta, 17, True)
+        n, chains = 1500, 3
+    burn = n // 5
+    G = orc.gram(d.X)
+    gpu, ora = [], []
+    for c in range(chains):
+        s = hsp.Sampler(torch.from_numpy(d.X).cuda(), torch.from_numpy(d.y).cuda(), seed=101 + c,
+                        max_draws=n)
+        s.sweep(n)
+        b, _, _ = s.draws()
+        gpu.append(b[burn:])
+        s.close()
+        ch = orc.Chain(d.p)
+        bo, _ = ch.run(d.X, d.y, G, seed=201 + c, n=n)
+        ora.append(bo[burn:])
+    mg, smg, vg, svg = pooled(gpu)
+    mo, smo, vo, svo = pooled(ora)
+    assert np.all(np.abs(mg - mo) <= 4 * np.sqrt(smg**2 + smo**2) + 1e-12)
+    assert np.all(np.abs(vg - vo) <= 4 * np.sqrt(svg**2 + svo**2) + 1e-12)
+    nz = np.flatnonzero(d.beta_true)
+    allg = np.concatenate(gpu)
+    lo, hi = np.quantile(allg[:, nz], 0.05, axis=0), np.quantile(allg[:, nz], 0.95, axis=0)
+    big = np.abs(d.beta_true[nz]) > 0.5
+    assert np.all((np.sign(lo) == np.sign(d.beta_true[nz]))[big])
+    assert np.all((np.sign(hi) == np.sign(d.beta_true[nz]))[big])
+
+
+def test_full_size_workload(env, orc):
+    torch, hsp = env
+    d = synth.config3()
+    s = hsp.Sampler(d.X, d.y, seed=1, debug_store_z=True, max_draws=64)
+    rng = np.random.default_rng(5)
+    # G on sampled entries (the oracle sums each entry over all rows)
+    G = s.gram()
+    for _ in range(24):
+        j, k = rng.integers(0, d.p, 2)
+        ref = orc.gram_entry(d.X, int(j), int(k))
+        assert abs(G[j, k] - ref) <= 1e-12 * math.sqrt(G[j, j] * G[k, k])
+    # one z step at a state with realistic |x_i beta|
+    beta = np.zeros(d.p)
+    beta[d.beta_true != 0] = d.beta_true[d.beta_true != 0]
+    beta += rng.normal(0, 0.01, d.p)
+    s.set_state(beta, np.ones(d.p), np.ones(d.p), 1.0, 1.0, 30)
+    s.step(hsp.HSP_STEP_Z)
+    z, att, b = s.debug()
+    zo, ao, bo = orc.z_step(d.X, d.y, beta, 1, 31)
+    assert np.all(z * (2.0 * d.y - 1.0) > 0)
+    flips = ((att & ~(1 << 30)) != ao) | (((att & (1 << 30)) != 0) != (bo == 1))
+    assert flips.sum() <= int(1e-5 * d.N)
+    ok = ~flips
+    assert np.max(np.abs(z[ok] - zo[ok]) / z_scale(d.X[ok], beta)) < 1e-5
+    if flips.sum() == 0:
+        assert np.max(np.abs(b - orc.xtz(d.X, zo)) / b_scale(d.X, zo)) < 1e-5
+    # 50 whole sweeps from the cold start, as timed by the benchmark
+    s.set_state(np.zeros(d.p), np.ones(d.p), np.ones(d.p), 1.0, 1.0, 0)
+    s.sweep(50)
+    z, att, b = s.debug()
+    assert np.all(z * (2.0 * d.y - 1.0) > 0)
+    betas, taus, n = s.draws()
+    assert n == 50 and np.all(np.isfinite(betas)) and np.all(taus > 0)
+    clamps, maxatt = s.counters()
+    assert clamps == 0 and maxatt < 64
+    # the chain has moved towards the truth on the nonzero coefficients
+    nz = np.flatnonzero(d.beta_true)
+    assert np.corrcoef(betas[-1][nz], d.beta_true[nz])[0, 1] > 0.9
+    s.close()
