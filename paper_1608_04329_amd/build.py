@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhsp.so")
-SOURCES = ["api.hip", "sweep.hip", "gram.hip"]
+SOURCES = ["api.hip", "sweep.hip", "gram.hip", "schedule.cpp"]
 ARCH = os.environ.get("HSP_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -21,9 +21,13 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     objs = []
     procs = []
     for src in SOURCES:
-        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = ["hipcc", "-c", *[f for f in FLAGS if f != "-shared"], "-o", obj,
-               os.path.join(CSRC, src)]
+        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
+        if src.endswith(".cpp"):  # host-only C++
+            cmd = ["hipcc", "-c", "-O2", "-std=c++17", "-fPIC", "-Wall", "-o", obj,
+                   os.path.join(CSRC, src)]
+        else:
+            cmd = ["hipcc", "-c", *[f for f in FLAGS if f != "-shared"], "-o", obj,
+                   os.path.join(CSRC, src)]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd), src))

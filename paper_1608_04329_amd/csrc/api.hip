@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -31,6 +32,7 @@ struct hsp_state {
     double *b = nullptr, *G = nullptr, *Gp = nullptr, *A = nullptr, *Linv = nullptr, *Dinv = nullptr;
     double *vec = nullptr, *partial = nullptr, *gpartial = nullptr;
     uint32_t* zgrp_count = nullptr;
+    uint32_t *tasks = nullptr, *task_off = nullptr, *ver = nullptr;  // tile path schedule
     float* beta32 = nullptr;
     float* zdbg = nullptr;
     int32_t* adbg = nullptr;
@@ -43,6 +45,7 @@ struct hsp_state {
     bool poisoned = false;
     hipGraphExec_t graph = nullptr;  // one whole sweep (one kernel), recording
     uint64_t* trace = nullptr;        // p-side phase timestamps (diagnostics)
+    SweepArgs* dargs = nullptr;       // [0]: a whole sweep, [1]: the last hsp_step
     bool timing = false;
     std::vector<hipEvent_t> ev;  // per timed sweep: start, end
     int64_t timed_sweeps = 0;
@@ -100,6 +103,9 @@ SweepArgs sweep_args(hsp_state* s, uint32_t mode) {
     a.A = s->A;
     a.Linv = s->Linv;
     a.Dinv = s->Dinv;
+    a.tasks = s->tasks;
+    a.task_off = s->task_off;
+    a.ver = s->ver;
     a.vec = s->vec;
     a.ring_beta = s->ring_beta;
     a.ring_tau = s->ring_tau;
@@ -112,14 +118,24 @@ SweepArgs sweep_args(hsp_state* s, uint32_t mode) {
     a.mode = mode;
     a.timeout_ticks = s->timeout_ticks;
     a.trace = s->trace;
+    a.gp = a.gz = a.zgroups = 0;
     return a;
+}
+
+// Upload the launch description of `mode` into device slot `slot`.
+hipError_t put_args(hsp_state* s, uint32_t mode, int slot, SweepArgs* out) {
+    *out = sweep_args(s, mode);
+    sweep_finish_args(out, s->plan);
+    return hipMemcpy(s->dargs + slot, out, sizeof(SweepArgs), hipMemcpyHostToDevice);
 }
 
 constexpr uint32_t kModeSweep =
     kModeZ | kModeLambda | kModeTau | kModeBeta | kModeNuXi | kModeRecord | kModeAdvance;
 
 hipError_t enqueue_sweep(hsp_state* s, hipStream_t st) {
-    return sweep_launch(sweep_args(s, kModeSweep), s->plan, st);
+    SweepArgs h = sweep_args(s, kModeSweep);
+    sweep_finish_args(&h, s->plan);
+    return sweep_launch(h, s->dargs, s->plan, st);
 }
 
 hipError_t capture(hsp_state* s, hipGraphExec_t* out) {
@@ -169,7 +185,7 @@ void free_state(hsp_state* s) {
     void* bufs[] = {s->Xbuf, s->y, s->ctrl, s->beta, s->lam, s->nu, s->tau, s->xi, s->b, s->G, s->Gp,
                     s->A, s->Linv, s->Dinv, s->vec, s->partial, s->beta32, s->zdbg, s->adbg,
                     s->ring_beta, s->ring_tau, s->ring_lam, s->trace, s->gpartial,
-                    s->zgrp_count};
+                    s->zgrp_count, s->dargs, s->tasks, s->task_off, s->ver};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
@@ -291,6 +307,18 @@ hsp_status create_impl(hsp_state* s, const float* X, const uint8_t* y, int64_t N
     }
 
     HIP_TRY(sweep_plan(s->x, s->num_cus, &s->plan));
+    if (p > kSmallP) {
+        // the factorisation's task lists for the group, and its tile versions
+        const uint32_t nt = (uint32_t)(P / kTile);
+        std::vector<uint32_t> tasks, off;
+        chol_schedule(nt, s->plan.gp, &tasks, &off);
+        HIP_TRY(dalloc(&s->tasks, tasks.size()));
+        HIP_TRY(dalloc(&s->task_off, off.size()));
+        HIP_TRY(dalloc(&s->ver, 2 * (size_t)nt * nt));
+        HIP_TRY(hipMemcpy(s->tasks, tasks.data(), tasks.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(s->task_off, off.data(), off.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemsetAsync(s->ver, 0, 2 * (size_t)nt * nt * 4, s->stream));
+    }
     HIP_TRY(dalloc(&s->partial, (size_t)s->plan.gz * ld));
     {
         const size_t ng = (s->plan.gz + kZGroup - 1) / kZGroup;
@@ -310,6 +338,11 @@ hsp_status create_impl(hsp_state* s, const float* X, const uint8_t* y, int64_t N
     HIP_TRY(dalloc(&s->ring_tau, cap));
     if (s->opt.record_lambda) HIP_TRY(dalloc(&s->ring_lam, cap * p));
 
+    HIP_TRY(dalloc(&s->dargs, 2));
+    {
+        SweepArgs h;
+        HIP_TRY(put_args(s, kModeSweep, 0, &h));
+    }
     HIP_TRY(hipStreamSynchronize(s->stream));
     // cold start (Section 6.1)
     std::vector<double> zeros(p, 0.0), ones(p, 1.0);
@@ -497,7 +530,10 @@ hsp_status hsp_step(hsp_state* s, uint32_t which) {
     if (which & HSP_STEP_BETA) mode |= kModeBeta;
     if (which & HSP_STEP_NUXI) mode |= kModeNuXi;
     if (which & HSP_STEP_ADVANCE) mode |= kModeAdvance;
-    HIP_TRY(sweep_launch(sweep_args(s, mode), s->plan, s->stream));
+    SweepArgs h;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(put_args(s, mode, 1, &h));
+    HIP_TRY(sweep_launch(h, s->dargs + 1, s->plan, s->stream));
     hsp_status st = sync_state(s);
     if (st) return st;
     if (which & HSP_STEP_ADVANCE) {
@@ -591,6 +627,8 @@ hsp_status hsp_set_phase_trace(hsp_state* s, int32_t enable) {
         HIP_TRY(hipMemsetAsync(s->trace, 0, (size_t)kMaxGroup * kTraceSlots * 8, s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
     }
+    SweepArgs h;
+    HIP_TRY(put_args(s, kModeSweep, 0, &h));
     return HSP_OK;
 }
 
@@ -621,6 +659,20 @@ hsp_status hsp_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* o
     (void)hipFree(dc);
     if (dout) (void)hipFree(dout);
     HIP_TRY(e);
+    return HSP_OK;
+}
+
+hsp_status hsp_tile_schedule(int64_t nt, int64_t gp, uint32_t* tasks, int64_t cap, uint32_t* off,
+                             int64_t* n_tasks) {
+    if (nt < 1 || nt > kMaxP / kTile || gp < 1 || gp > 4096 || !n_tasks)
+        return fail(nullptr, HSP_EINVAL, "bad arguments");
+    std::vector<uint32_t> t, o;
+    chol_schedule((uint32_t)nt, (uint32_t)gp, &t, &o);
+    *n_tasks = (int64_t)t.size();
+    if ((int64_t)t.size() > cap || !tasks || !off)
+        return fail(nullptr, HSP_ERANGE, "task buffer too small");
+    std::copy(t.begin(), t.end(), tasks);
+    std::copy(o.begin(), o.end(), off);
     return HSP_OK;
 }
 

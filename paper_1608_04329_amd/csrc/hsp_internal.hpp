@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace hsp {
 
 constexpr int kWave = 64;
@@ -13,10 +15,11 @@ constexpr int kTile = 64;              // p-side tile edge
 constexpr int kSmallP = 128;           // p up to this runs the one-block p-side path
 constexpr int kMaxGroup = 32;          // most blocks of the p-side group
 constexpr int kZGroup = 16;            // z-pass blocks whose partials one block sums
-// LDS of one sweep-kernel block: two 64 x 65 float64 tiles (66,560 bytes).  The
-// same buffer holds the z pass's reduction segment and the packed Q of the
-// one-block path (p (p + 1) / 2 <= 8256 doubles for p <= 128).
-constexpr int kLdsDoubles = 2 * kTile * (kTile + 1);
+// LDS of one sweep-kernel block: two 64 x 66 float64 tiles (67,584 bytes; rows
+// 16-byte aligned).  The same buffer holds the z pass's reduction segment and
+// the packed Q of the one-block path (p (p + 1) / 2 <= 8256 doubles).
+constexpr int kTileLd = kTile + 2;
+constexpr int kLdsDoubles = 2 * kTile * kTileLd;
 
 // Device control block, one per sampler state.
 struct Ctrl {
@@ -98,9 +101,32 @@ struct SweepArgs {
     uint32_t zgroups;        // ceil(gz / kZGroup)
     uint64_t timeout_ticks;  // bound of every wait, in s_memrealtime ticks
     uint64_t* trace;         // optional: kTraceSlots timestamps per group block
+    const uint32_t* tasks;   // tile path: every group block's task list, concatenated
+    const uint32_t* task_off;  // gp + 1 offsets into tasks
+    uint32_t* ver;           // tile path: 2 x nt x nt tile version counters (zero between launches)
 };
 
-constexpr int kTraceSlots = 128;
+// Diagnostic trace per group block: slot 0 = start, slots 1.. one timestamp per
+// event in order (group barriers; per factorisation task: inputs ready, done),
+// then kTraceRecs records of kTraceRec slots for the diagonal tiles the block
+// factored (loaded, panels, inverse, stored), and the last slot = z pass seen
+// complete.
+constexpr int kTraceSlots = 256;
+constexpr int kTraceSeq = 192;
+constexpr int kTraceRec = 12;
+constexpr int kTraceRecs = 5;
+
+// ---- tasks of the tiled factorisation (p > 128) ----------------------------------
+enum : uint32_t { kTaskPotrf = 0u, kTaskTrsm = 1u, kTaskGemm = 2u };
+// type (2 bits) | part (0: U, 1: L^-1) | step k | tile row i | tile column j (7 bits each)
+__host__ __device__ constexpr uint32_t task_code(uint32_t type, uint32_t part, uint32_t k, uint32_t i,
+                                                 uint32_t j) {
+    return type | part << 2 | k << 3 | i << 10 | j << 17;
+}
+// Per-block task lists of the factorisation of [Q | I] over gp blocks
+// (schedule.cpp): tasks[off[b] .. off[b + 1]) are block b's, in order.
+void chol_schedule(uint32_t nt, uint32_t gp, std::vector<uint32_t>* tasks,
+                   std::vector<uint32_t>* off);
 
 struct SweepPlan {
     uint32_t gp;
@@ -112,8 +138,11 @@ struct SweepPlan {
 
 // Plan a launch for X's shape; num_cus from the device.
 hipError_t sweep_plan(const XLayout& x, int num_cus, SweepPlan* plan);
-// Enqueue one launch of the sweep kernel.
-hipError_t sweep_launch(const SweepArgs& a, const SweepPlan& plan, hipStream_t st);
+// Fill gp, gz and zgroups of a launch description from the plan and its mode.
+void sweep_finish_args(SweepArgs* a, const SweepPlan& plan);
+// Enqueue one launch of the sweep kernel; dev is a device copy of host.
+hipError_t sweep_launch(const SweepArgs& host, const SweepArgs* dev, const SweepPlan& plan,
+                        hipStream_t st);
 
 // G = X^T X (p x p float64, leading dimension p); work must hold
 // gram_work_doubles(x) doubles.

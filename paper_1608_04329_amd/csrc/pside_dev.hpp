@@ -41,6 +41,8 @@ struct Group {
     unsigned long long zbase;  // z_count when this launch started
     uint32_t size;
     uint32_t n;                // barriers passed
+    uint32_t slot;             // next trace slot
+    uint32_t npotrf;           // diagonal tiles factored by this block
     uint64_t timeout;
 };
 
@@ -71,6 +73,34 @@ __device__ __forceinline__ void wait_count(unsigned long long* ctr, unsigned lon
     }
 }
 
+// Thread 0: next trace timestamp (diagnostics only).
+__device__ __forceinline__ void stamp(Group& g) {
+    if (g.trace && threadIdx.x == 0 && g.slot + 1 < (uint32_t)kTraceSeq) g.trace[++g.slot] = wall_clock64();
+}
+
+// Thread 0: timestamp into slot s of a diagonal-factorisation record (or none).
+__device__ __forceinline__ void stamp_at(uint64_t* rec, int s) {
+    if (rec && threadIdx.x == 0) rec[s] = wall_clock64();
+}
+
+// Thread 0 only: wait until *ver >= need; false if the group is failing or
+// the wait timed out.
+__device__ __forceinline__ bool wait_ver(uint32_t* ver, uint32_t need, Ctrl* ctrl, uint64_t timeout) {
+    if (__hip_atomic_load(ver, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= need) return true;
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(ver, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        if (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+            (kErrTimeout | kErrNotPD))
+            return false;
+        if (wall_clock64() - t0 > timeout) {
+            atomicOr(&ctrl->err, kErrTimeout);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+
 __device__ __forceinline__ void group_sync(Group& g) {
     __threadfence();
     __syncthreads();
@@ -83,7 +113,7 @@ __device__ __forceinline__ void group_sync(Group& g) {
         atomicAdd(&g.ctrl->bar_count, 1ull);
     }
     g.n++;
-    if (g.trace && threadIdx.x == 0 && g.n < kTraceSlots - 1) g.trace[g.n] = wall_clock64();
+    stamp(g);
     __syncthreads();
 }
 
@@ -100,7 +130,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return s;
 }
 
-__device__ __forceinline__ uint32_t record_slot(const SweepArgs a, uint32_t k, bool* keep) {
+__device__ __forceinline__ uint32_t record_slot(const SweepArgs& a, uint32_t k, bool* keep) {
     const uint32_t since = k - a.ctrl->draw_base;
     *keep = (a.mode & kModeRecord) && since % a.thin == 0;
     return *keep ? (since / a.thin - 1u) % a.capacity : 0u;
@@ -108,7 +138,7 @@ __device__ __forceinline__ uint32_t record_slot(const SweepArgs a, uint32_t k, b
 
 // ---- lambda^-2 and tau^-2 (every block of the group computes them) ---------------
 // Returns tau^-2 (new if kModeTau).  Block `writer` stores lambda^-2 and tau^-2.
-__device__ double hyper_lambda_tau(const SweepArgs a, uint32_t k, bool writer, double* red) {
+__device__ double hyper_lambda_tau(const SweepArgs& a, uint32_t k, bool writer, double* red) {
     const uint32_t p = a.x.p;
     const double tau_old = *a.tau_m2;
     double acc = 0.0;
@@ -182,7 +212,7 @@ __device__ double hyper_lambda_tau(const SweepArgs a, uint32_t k, bool writer, d
 }
 
 // tau^-2 of this sweep: the scratch slot if it was drawn in this launch.
-__device__ __forceinline__ double current_tau(const SweepArgs a) {
+__device__ __forceinline__ double current_tau(const SweepArgs& a) {
     // written by block 0 of the group in this launch: read past the scalar cache
     return (a.mode & kModeTau)
                ? __hip_atomic_load(a.vec + 2 * a.x.p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
@@ -190,7 +220,7 @@ __device__ __forceinline__ double current_tau(const SweepArgs a) {
 }
 
 // nu^-1 and xi^-1 from the (new) lambda^-2 and tau^-2 in memory.
-__device__ void hyper_nu_xi(const SweepArgs a, uint32_t k) {
+__device__ void hyper_nu_xi(const SweepArgs& a, uint32_t k) {
     const uint32_t p = a.x.p;
     for (uint32_t j = threadIdx.x; j < p; j += kThreads) {
         const Words4 w = draw_words(a.seed, j, k, kTagNu, 0, a.chain);
@@ -204,7 +234,7 @@ __device__ void hyper_nu_xi(const SweepArgs a, uint32_t k) {
 
 // b = sum of the z-pass groups' partial rows, columns [c0, c1) by this block,
 // 16 columns x 16 row groups at a time, in a fixed order.
-__device__ void reduce_b_cols(const SweepArgs a, uint32_t c0, uint32_t c1, double* red) {
+__device__ void reduce_b_cols(const SweepArgs& a, uint32_t c0, uint32_t c1, double* red) {
     const int tc = threadIdx.x & 15, tr = threadIdx.x >> 4;
     for (uint32_t cb = c0; cb < c1; cb += 16) {
         const uint32_t col = cb + tc;
@@ -262,7 +292,7 @@ __device__ void wave_solve(const double* U, uint32_t p, double (&r)[2], bool for
     }
 }
 
-__device__ void small_path(const SweepArgs a, Group& g, uint32_t k, double* lds) {
+__device__ void small_path(const SweepArgs& a, Group& g, uint32_t k, double* lds) {
     const uint32_t p = a.x.p;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     double tau = hyper_lambda_tau(a, k, true, lds);
@@ -367,7 +397,10 @@ __device__ void small_path(const SweepArgs a, Group& g, uint32_t k, double* lds)
 // leading dimension P: Gp holds G with an identity block on the padding, so
 // the factor, L^-1 and Q^-1 carry an identity block there too and no tile
 // ever needs a bounds check.
-typedef double Tile[kTile][kTile + 1];
+#ifndef HSP_TILE_MFMA
+#define HSP_TILE_MFMA 1
+#endif
+typedef double Tile[kTile][kTileLd];
 
 __device__ __forceinline__ uint32_t padded(uint32_t p) { return (p + kTile - 1) / kTile * kTile; }
 
@@ -394,22 +427,117 @@ __device__ __forceinline__ void load_tile(Tile& T, const double* M, uint32_t P, 
     for (int q = 0; q < 16; ++q) T[rb + 4 * q][c] = v[q];
 }
 
-// acc[t][u] = sum_q S[q][ty*4+t] * T[q][tx*4+u]  (a 64 x 64 x 64 product S^T T)
+// load_tile for two tiles with every global load issued before any LDS store.
+__device__ __forceinline__ void load_tiles(Tile& S, const double* MS, uint32_t rs, uint32_t cs,
+                                           Tile& T, const double* MT, uint32_t rt, uint32_t ct,
+                                           uint32_t P) {
+    const int c = threadIdx.x & (kTile - 1), rb = threadIdx.x >> 6;
+    const double* s0 = MS + (size_t)(rs + rb) * P + cs + c;
+    const double* t0 = MT + (size_t)(rt + rb) * P + ct + c;
+    double v[16], w[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        v[q] = s0[(size_t)(4 * q) * P];
+        w[q] = t0[(size_t)(4 * q) * P];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        S[rb + 4 * q][c] = v[q];
+        T[rb + 4 * q][c] = w[q];
+    }
+}
+
+// acc[t][u] = sum_q S[q][ty*4+t] * T[q][tx*4+u]  (a 64 x 64 x 64 product S^T T).
+// Rows are 16-byte aligned: each thread reads its 4 + 4 operands per q with
+// four 16-byte LDS loads.
 __device__ __forceinline__ void gemm_tn(const Tile& S, const Tile& T, double (&acc)[4][4]) {
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 #pragma unroll 4
     for (int q = 0; q < kTile; ++q) {
-        double s[4], v[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            s[t] = S[q][ty * 4 + t];
-            v[t] = T[q][tx * 4 + t];
-        }
+        const double2* sp = reinterpret_cast<const double2*>(&S[q][ty * 4]);
+        const double2* tp = reinterpret_cast<const double2*>(&T[q][tx * 4]);
+        const double2 s01 = sp[0], s23 = sp[1], v01 = tp[0], v23 = tp[1];
+        const double s[4] = {s01.x, s01.y, s23.x, s23.y};
+        const double v[4] = {v01.x, v01.y, v23.x, v23.y};
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int u = 0; u < 4; ++u) acc[t][u] = fma(s[t], v[u], acc[t][u]);
     }
+}
+
+// ---- the same 64 x 64 x 64 products on the FP64 matrix cores ----------------
+// v_mfma_f64_16x16x4f64 computes D(16x16) += A(16x4) B(4x16); lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[l / 16 + 4 r][l % 16]
+// in its r-th result.  Wave w owns the 32 x 32 quadrant at rows 32 (w / 2),
+// columns 32 (w % 2) as 2 x 2 blocks of 16 x 16; per k-step of 4 it reads
+// four 64-lane fragments from LDS for four matrix operations.
+typedef double Acc4 __attribute__((ext_vector_type(4)));
+struct MAcc {
+    Acc4 v[2][2];
+};
+
+__device__ __forceinline__ void gemm_tn_mfma(const Tile& S, const Tile& T, MAcc& acc) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i0 = 32 * (wave >> 1), j0 = 32 * (wave & 1);
+    const int kr = lane >> 4, cc = lane & 15;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc.v[bi][bj] = Acc4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int q0 = 0; q0 < kTile; q0 += 4) {
+        const double a0 = S[q0 + kr][i0 + cc], a1 = S[q0 + kr][i0 + 16 + cc];
+        const double b0 = T[q0 + kr][j0 + cc], b1 = T[q0 + kr][j0 + 16 + cc];
+        acc.v[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.v[0][0], 0, 0, 0);
+        acc.v[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.v[0][1], 0, 0, 0);
+        acc.v[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.v[1][0], 0, 0, 0);
+        acc.v[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.v[1][1], 0, 0, 0);
+    }
+}
+
+// store_tile for the matrix-core layout: sixteen values per lane, each a
+// 128-byte row segment across 16 lanes.
+__device__ __forceinline__ void store_tile_m(double* M, uint32_t P, uint32_t r0, uint32_t c0,
+                                             const MAcc& acc, double sign, const double* src,
+                                             bool add_diag, double tau, const double* lam,
+                                             uint32_t p) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t ri = r0 + 32 * (wave >> 1) + (lane >> 4);
+    const uint32_t cj = c0 + 32 * (wave & 1) + (lane & 15);
+    double out[2][2][4];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[bi][bj][r] = src ? src[(size_t)(ri + 16 * bi + 4 * r) * P + cj + 16 * bj] : 0.0;
+    if (add_diag) {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t gi = ri + 16 * bi + 4 * r, gj = cj + 16 * bj;
+                    if (gi == gj && gi < p) out[bi][bj][r] += tau * lam[gi];
+                }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[bi][bj][r] = fma(sign, acc.v[bi][bj][r], out[bi][bj][r]);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                M[(size_t)(ri + 16 * bi + 4 * r) * P + cj + 16 * bj] = out[bi][bj][r];
 }
 
 __device__ __forceinline__ void zero_acc(double (&acc)[4][4]) {
@@ -454,17 +582,6 @@ __device__ __forceinline__ void store_tile(double* M, uint32_t P, uint32_t r0, u
         for (int u = 0; u < 4; ++u) M[base + (size_t)t * P + u] = out[t][u];
 }
 
-// The transpose of acc into M(c0.., r0..) (for symmetric results).
-__device__ __forceinline__ void store_tile_t(double* M, uint32_t P, uint32_t r0, uint32_t c0,
-                                             const double (&acc)[4][4]) {
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            M[(size_t)(c0 + tx * 4 + u) * P + r0 + ty * 4 + t] = acc[t][u];
-}
-
 // Inverse of the upper-triangular 64 x 64 U (in S) into T, by recursive
 // doubling: T starts as diag(1/U_ii); for b = 1, 2, ..., 32 every diagonal
 // 2b-block [U1 U12; 0 U2] gets W12 = -W1 (U12 W2).  U12 W2 is parked in the
@@ -505,13 +622,21 @@ __device__ __forceinline__ void inverse_level(const Tile& S, Tile& T) {
 //
 // Four row panels of 16.  For each, wave 0 eliminates the panel in registers:
 // lane j holds the panel's 16 entries of column j; at step c the pivot is
-// lane (r0 + c)'s entry c, row c is scaled by 1/sqrt(pivot), and the panel
-// rows below lose U[c][i] times it (U[c][i] read from lane r0 + i).  That is
+// lane (r0 + c)'s entry c (a scalar read of one lane), row c is scaled by
+// 1/sqrt(pivot), and the panel rows below lose U[c][i] times it (U[c][i] read
+// from lane r0 + i).  That is
 // both the 16 x 16 factorisation and the solve of the panel's columns to the
 // right.  Then every wave subtracts the panel's contribution from the
 // trailing block.  Eight barriers.  Returns false on a non-positive pivot
 // (uniformly: the flag goes through LDS).
-__device__ bool factor_diag(Tile& S, Tile& T) {
+__device__ __forceinline__ double rdlane(double v, int l) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ bool factor_diag(Tile& S, Tile& T, uint64_t* rec) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double* flag = &T[kTile - 1][kTile];  // padding corner, not part of the tile
 #pragma unroll
@@ -524,18 +649,19 @@ __device__ bool factor_diag(Tile& S, Tile& T) {
             bool ok = true;
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
-                const double d = __shfl(a[c], r0 + c);
+                const double d = rdlane(a[c], r0 + c);
                 ok = ok && (d > 0.0);
                 const double rs = 1.0 / sqrt(d);
                 a[c] = lane == r0 + c ? d * rs : a[c] * rs;
 #pragma unroll
-                for (int i = c + 1; i < 16; ++i) a[i] = fma(-__shfl(a[c], r0 + i), a[c], a[i]);
+                for (int i = c + 1; i < 16; ++i) a[i] = fma(-rdlane(a[c], r0 + i), a[c], a[i]);
             }
 #pragma unroll
             for (int c = 0; c < 16; ++c) S[r0 + c][lane] = lane >= r0 + c ? a[c] : 0.0;
             if (lane == 0) *flag = ok ? 0.0 : 1.0;
         }
         __syncthreads();
+        stamp_at(rec, 1 + 2 * P);
         if (*flag != 0.0) return false;
         // trailing update: S[i][j] -= sum_c S[r0+c][i] S[r0+c][j], r0+16 <= i <= j
         constexpr int m0 = 0;
@@ -551,6 +677,7 @@ __device__ bool factor_diag(Tile& S, Tile& T) {
             }
         }
         __syncthreads();
+        stamp_at(rec, 2 + 2 * P);
     }
     // T = U^-1
     for (int e = threadIdx.x; e < kTile * kTile; e += kThreads) {
@@ -569,19 +696,23 @@ __device__ bool factor_diag(Tile& S, Tile& T) {
         if (c < r) T[r][c] = 0.0;
     }
     __syncthreads();
+    stamp_at(rec, 9);
     return true;
 }
 
 // Factor diagonal block kb: load it (from Gp + tau Lambda for kb = 0), factor,
-// store U_kk into A and its inverse into Dinv[kb].  Reports a failed pivot.
-__device__ void diag_block(const SweepArgs a, uint32_t kb, double tau, Tile& S, Tile& T) {
+// store U_kk into A, its inverse D into Dinv[kb] and D^T = L^-1_kk into Linv.
+// Reports a failed pivot.
+__device__ void diag_block(const SweepArgs& a, uint32_t kb, double tau, Tile& S, Tile& T,
+                           uint64_t* rec) {
     const uint32_t p = a.x.p, P = padded(p), k0 = kb * kTile;
     load_tile(S, kb == 0 ? a.Gp : a.A, P, k0, k0, kb == 0, tau, a.lam_m2, p);
     __syncthreads();
     for (int e = threadIdx.x; e < kTile * kTile; e += kThreads)
         if (e % kTile < e / kTile) S[e / kTile][e % kTile] = 0.0;
     __syncthreads();
-    if (factor_diag(S, T)) {
+    stamp_at(rec, 0);
+    if (factor_diag(S, T, rec)) {
         double* D = a.Dinv + (size_t)kb * kTile * kTile;
         const int c = threadIdx.x & (kTile - 1), rb = threadIdx.x >> 6;
 #pragma unroll
@@ -589,12 +720,14 @@ __device__ void diag_block(const SweepArgs a, uint32_t kb, double tau, Tile& S, 
             const int r = rb + 4 * q;
             a.A[(size_t)(k0 + r) * P + k0 + c] = S[r][c];
             D[r * kTile + c] = T[r][c];
+            a.Linv[(size_t)(k0 + r) * P + k0 + c] = T[c][r];
         }
     } else if (threadIdx.x == 0) {
         atomicOr(&a.ctrl->err, kErrNotPD);
         atomicCAS(&a.ctrl->chol_info, 0, (int)(k0 + 1));
     }
     __syncthreads();
+    stamp_at(rec, 10);
 }
 
 // Decode update tile t of step kb: A-part tiles (i, j), kb < i <= j, come first,
@@ -618,12 +751,129 @@ __device__ __forceinline__ bool update_tile(uint32_t t, uint32_t kb, uint32_t nt
     return false;
 }
 
-__device__ void tile_path(const SweepArgs a, Group& g, uint32_t rank, uint32_t k, double* lds) {
+// Run block `rank`'s list of factorisation tasks.  Tile versions: U tile
+// (i, j), i <= j, has had v of its i updates (plus 1 once final); L^-1 tile
+// (i, j), j <= i, v of its i - j updates (plus 1 once final).  Each task waits
+// for the versions it reads, then publishes the version it wrote.  Returns
+// false if the group is failing.
+__device__ bool run_tasks(const SweepArgs& a, Group& g, uint32_t rank, double tau, Tile& S, Tile& T,
+                          double* flag) {
+    const uint32_t p = a.x.p, P = padded(p), nt = P / kTile;
+    uint32_t* vU = a.ver;
+    uint32_t* vL = a.ver + nt * nt;
+    const uint32_t n0 = a.task_off[rank], n1 = a.task_off[rank + 1];
+    for (uint32_t n = n0; n < n1; ++n) {
+        const uint32_t code = a.tasks[n];
+        const uint32_t type = code & 3u, part = (code >> 2) & 1u, kb = (code >> 3) & 127u,
+                       ib = (code >> 10) & 127u, jb = (code >> 17) & 127u;
+        if (threadIdx.x == 0) {
+            bool w = true;
+            if (type == kTaskPotrf) {
+                w = wait_ver(&vU[kb * nt + kb], kb, a.ctrl, g.timeout);
+            } else if (type == kTaskTrsm) {
+                w = wait_ver(&vU[kb * nt + kb], kb + 1, a.ctrl, g.timeout) &&
+                    (part == 0 ? wait_ver(&vU[kb * nt + jb], kb, a.ctrl, g.timeout)
+                               : wait_ver(&vL[kb * nt + jb], kb - jb, a.ctrl, g.timeout));
+            } else {
+                w = wait_ver(&vU[kb * nt + ib], kb + 1, a.ctrl, g.timeout) &&
+                    (part == 0 ? wait_ver(&vU[kb * nt + jb], kb + 1, a.ctrl, g.timeout) &&
+                                     wait_ver(&vU[ib * nt + jb], kb, a.ctrl, g.timeout)
+                               : wait_ver(&vL[kb * nt + jb], kb - jb + 1, a.ctrl, g.timeout) &&
+                                     wait_ver(&vL[ib * nt + jb], kb - jb, a.ctrl, g.timeout));
+            }
+            *flag = w ? 0.0 : 1.0;
+            __threadfence();
+        }
+        __syncthreads();
+        stamp(g);
+        if (*flag != 0.0) return false;
+        const uint32_t k0 = kb * kTile;
+        uint32_t* out = nullptr;
+        uint32_t val = 0;
+        if (type == kTaskPotrf) {
+            uint64_t* rec = nullptr;
+            if (g.trace && g.npotrf < (uint32_t)kTraceRecs) rec = g.trace + kTraceSeq + kTraceRec * g.npotrf;
+            g.npotrf++;
+            diag_block(a, kb, tau, S, T, rec);
+            if (threadIdx.x == 0 &&
+                (__hip_atomic_load(&a.ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrNotPD))
+                *flag = 1.0;
+            __syncthreads();
+            if (*flag != 0.0) return false;
+            if (threadIdx.x == 0)
+                __hip_atomic_store(&vL[kb * nt + kb], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            out = &vU[kb * nt + kb];
+            val = kb + 1;
+        } else if (type == kTaskTrsm) {
+            // row kb times D = U_kk^-1: X_kj = D^T X_kj
+            const double* Dk = a.Dinv + (size_t)kb * kTile * kTile;
+            const uint32_t j0 = jb * kTile;
+            const int c = threadIdx.x & (kTile - 1), rb = threadIdx.x >> 6;
+            const double* src = (part == 0 ? (kb == 0 ? a.Gp : a.A) : a.Linv) + (size_t)(k0 + rb) * P + j0 + c;
+            double v[16], x[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                v[q] = Dk[(rb + 4 * q) * kTile + c];
+                x[q] = src[(size_t)(4 * q) * P];
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                S[rb + 4 * q][c] = v[q];
+                T[rb + 4 * q][c] = x[q];
+            }
+            __syncthreads();
+#if HSP_TILE_MFMA
+            MAcc acc;
+            gemm_tn_mfma(S, T, acc);
+            store_tile_m(part == 0 ? a.A : a.Linv, P, k0, j0, acc, 1.0, nullptr, false, 0.0, nullptr, p);
+#else
+            double acc[4][4];
+            zero_acc(acc);
+            gemm_tn(S, T, acc);
+            store_tile(part == 0 ? a.A : a.Linv, P, k0, j0, acc, 1.0, nullptr, false, 0.0, nullptr, p);
+#endif
+            out = part == 0 ? &vU[kb * nt + jb] : &vL[kb * nt + jb];
+            val = part == 0 ? kb + 1 : kb - jb + 1;
+        } else {
+            // A_ij -= U_ki^T U_kj  or  L^-1_ij -= U_ki^T L^-1_kj
+            load_tiles(S, a.A, k0, ib * kTile, T, part == 0 ? a.A : a.Linv, k0, jb * kTile, P);
+            __syncthreads();
+#if HSP_TILE_MFMA
+            MAcc acc;
+            gemm_tn_mfma(S, T, acc);
+            if (part == 0)
+                store_tile_m(a.A, P, ib * kTile, jb * kTile, acc, -1.0, kb == 0 ? a.Gp : a.A,
+                             kb == 0 && ib == jb, tau, a.lam_m2, p);
+            else
+                store_tile_m(a.Linv, P, ib * kTile, jb * kTile, acc, -1.0, jb == kb ? nullptr : a.Linv,
+                             false, 0.0, nullptr, p);
+#else
+            double acc[4][4];
+            zero_acc(acc);
+            gemm_tn(S, T, acc);
+            if (part == 0)
+                store_tile(a.A, P, ib * kTile, jb * kTile, acc, -1.0, kb == 0 ? a.Gp : a.A,
+                           kb == 0 && ib == jb, tau, a.lam_m2, p);
+            else
+                store_tile(a.Linv, P, ib * kTile, jb * kTile, acc, -1.0, jb == kb ? nullptr : a.Linv,
+                           false, 0.0, nullptr, p);
+#endif
+            out = part == 0 ? &vU[ib * nt + jb] : &vL[ib * nt + jb];
+            val = part == 0 ? kb + 1 : kb - jb + 1;
+        }
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_store(out, val, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        stamp(g);
+    }
+    return true;
+}
+
+__device__ void tile_path(const SweepArgs& a, Group& g, uint32_t rank, uint32_t k, double* lds) {
     const uint32_t p = a.x.p, P = padded(p);
-    const uint32_t nt = P / kTile;
     Tile& S = *reinterpret_cast<Tile*>(lds);
-    Tile& T = *reinterpret_cast<Tile*>(lds + kTile * (kTile + 1));
-    double* flag = lds + 2 * kTile * (kTile + 1) - 1;  // T's unused padding corner
+    Tile& T = *reinterpret_cast<Tile*>(lds + kTile * kTileLd);
+    double* flag = lds + 2 * kTile * kTileLd - 1;  // T's unused padding corner
     const double tau = hyper_lambda_tau(a, k, rank == 0, lds);
     group_sync(g);  // lambda^-2 and the new tau^-2 in memory
     double* s_noise = a.vec + p;
@@ -638,75 +888,11 @@ __device__ void tile_path(const SweepArgs a, Group& g, uint32_t rank, uint32_t k
 
     bool ok = true;
     if (a.mode & kModeBeta) {
-        // Factorisation of [Q | I]: U in A (upper), L^-1 = U^-T in Linv (lower).
-        if (rank == 0) diag_block(a, 0, tau, S, T);
+        // Factorisation of [Q | I]: U in A (upper), L^-1 = U^-T in Linv (lower),
+        // as this block's list of tile tasks.
+        ok = run_tasks(a, g, rank, tau, S, T, flag);
         group_sync(g);
-        ok = !group_failed(g, flag);
-        for (uint32_t kb = 0; ok && kb < nt; ++kb) {
-            const uint32_t k0 = kb * kTile;
-            // row kb times D = U_kk^-1 (transposed): U_kj = D^T A_kj (j > kb),
-            // Linv_kj = D^T Linv_kj (j < kb), Linv_kk = D^T
-            for (uint32_t j = rank; j < nt; j += g.size) {
-                const double* Dk = a.Dinv + (size_t)kb * kTile * kTile;
-                {
-                    const int c = threadIdx.x & (kTile - 1), rb = threadIdx.x >> 6;
-                    double v[16];
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) v[q] = Dk[(rb + 4 * q) * kTile + c];
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) S[rb + 4 * q][c] = v[q];
-                }
-                const uint32_t j0 = j * kTile;
-                if (j == kb) {
-                    __syncthreads();
-                    const int c = threadIdx.x & (kTile - 1), rb = threadIdx.x >> 6;
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        const int r = rb + 4 * q;
-                        a.Linv[(size_t)(k0 + r) * P + k0 + c] = S[c][r];
-                    }
-                    __syncthreads();
-                    continue;
-                }
-                if (j > kb) load_tile(T, kb == 0 ? a.Gp : a.A, P, k0, j0, false, 0.0, nullptr, p);
-                else load_tile(T, a.Linv, P, k0, j0, false, 0.0, nullptr, p);
-                __syncthreads();
-                double acc[4][4];
-                zero_acc(acc);
-                gemm_tn(S, T, acc);
-                store_tile(j > kb ? a.A : a.Linv, P, k0, j0, acc, 1.0, nullptr, false, 0.0, nullptr, p);
-                __syncthreads();
-            }
-            group_sync(g);
-            if (kb + 1 == nt) break;
-            // trailing update A_ij -= U_ki^T U_kj (kb < i <= j) and
-            // Linv_ij -= U_ki^T Linv_kj (i > kb, j <= kb; Linv_i,kb starts at 0).
-            // Tile 0 is (kb+1, kb+1): block 0 updates it alone and factors it
-            // at once (look-ahead), the other blocks share the rest.
-            const uint32_t m = nt - kb - 1;
-            const uint32_t ntiles = m * (m + 1) / 2 + m * (kb + 1);
-            for (uint32_t t = rank == 0 ? 0u : rank; t < ntiles; t += g.size - 1) {
-                uint32_t ib, jb;
-                const bool apart = update_tile(t, kb, nt, &ib, &jb);
-                load_tile(S, a.A, P, k0, ib * kTile, false, 0.0, nullptr, p);
-                load_tile(T, apart ? a.A : a.Linv, P, k0, jb * kTile, false, 0.0, nullptr, p);
-                __syncthreads();
-                double acc[4][4];
-                zero_acc(acc);
-                gemm_tn(S, T, acc);
-                if (apart)
-                    store_tile(a.A, P, ib * kTile, jb * kTile, acc, -1.0, kb == 0 ? a.Gp : a.A,
-                               kb == 0 && ib == jb, tau, a.lam_m2, p);
-                else
-                    store_tile(a.Linv, P, ib * kTile, jb * kTile, acc, -1.0,
-                               jb == kb ? nullptr : a.Linv, false, 0.0, nullptr, p);
-                __syncthreads();
-                if (rank == 0) break;  // block 0 owns tile 0 only
-            }
-            if (rank == 0) diag_block(a, kb + 1, tau, S, T);
-            group_sync(g);
-            ok = !group_failed(g, flag);
-        }
+        ok = ok && !group_failed(g, flag);
     }
 
     if (a.mode & kModeZ) {
@@ -787,7 +973,7 @@ __device__ void tile_path(const SweepArgs a, Group& g, uint32_t rank, uint32_t k
 }
 
 // The whole p-side role of block `rank` of the group.
-__device__ __forceinline__ void pside_role(const SweepArgs a, uint32_t rank, uint32_t k, double* lds) {
+__device__ __forceinline__ void pside_role(const SweepArgs& a, uint32_t rank, uint32_t k, double* lds) {
     Group g;
     g.trace = a.trace ? a.trace + (size_t)rank * kTraceSlots : nullptr;
     if (g.trace && threadIdx.x == 0) g.trace[0] = wall_clock64();
@@ -796,6 +982,8 @@ __device__ __forceinline__ void pside_role(const SweepArgs a, uint32_t rank, uin
     g.zbase = a.ctrl->z_epoch;
     g.size = a.gp;
     g.n = 0;
+    g.slot = 0;
+    g.npotrf = 0;
     g.timeout = a.timeout_ticks;
     if (a.x.p <= (uint32_t)kSmallP) small_path(a, g, k, lds);
     else tile_path(a, g, rank, k, lds);
@@ -808,8 +996,12 @@ __device__ __forceinline__ void pside_role(const SweepArgs a, uint32_t rank, uin
             if (a.mode & kModeZ) a.ctrl->z_epoch = g.zbase + a.zgroups;
             if (a.mode & kModeTau) *a.tau_m2 = current_tau(a);
             if (a.mode & kModeAdvance) a.ctrl->sweep = k;
-            __threadfence();
         }
+        if (a.x.p > (uint32_t)kSmallP && (a.mode & kModeBeta)) {
+            const uint32_t nt = padded(a.x.p) / kTile;
+            for (uint32_t e = threadIdx.x; e < 2 * nt * nt; e += kThreads) a.ver[e] = 0u;
+        }
+        __threadfence();
     }
 }
 

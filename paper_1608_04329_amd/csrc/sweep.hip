@@ -20,9 +20,13 @@
 namespace hsp {
 namespace {
 
+// The launch's description lives in device memory (read through the scalar
+// cache as needed) rather than in kernel arguments, which would otherwise stay
+// pinned in scalar registers for the whole kernel.
 template <int XT, int KC, int R>
-__global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
+__global__ __launch_bounds__(kThreads, 2) void sweep_kernel(const SweepArgs* __restrict__ args) {
     __shared__ double lds[kLdsDoubles];
+    const SweepArgs& a = *args;
     const uint32_t k = a.ctrl->sweep + 1u;
     if (blockIdx.x < a.gp) pside_role(a, blockIdx.x, k, lds);
     else zpass_role<XT, KC, R>(a, blockIdx.x - a.gp, a.gz, k, lds);
@@ -30,7 +34,7 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(SweepArgs a) {
 
 constexpr int rows_for_chunks(int kc) { return kc <= 4 ? 8 : (kc <= 8 ? 4 : 2); }
 
-using KernelFn = void (*)(SweepArgs);
+using KernelFn = void (*)(const SweepArgs*);
 
 template <int XT, int... KCs>
 KernelFn pick(int kc, std::integer_sequence<int, KCs...>) {
@@ -72,16 +76,19 @@ hipError_t sweep_plan(const XLayout& x, int num_cus, SweepPlan* plan) {
     return hipSuccess;
 }
 
-hipError_t sweep_launch(const SweepArgs& a0, const SweepPlan& plan, hipStream_t st) {
-    KernelFn f = kernel_for(a0.x.xtype, plan.chunks);
+void sweep_finish_args(SweepArgs* a, const SweepPlan& plan) {
+    a->gp = plan.gp;
+    a->gz = (a->mode & kModeZ) ? plan.gz : 0u;
+    a->zgroups = (a->gz + kZGroup - 1) / kZGroup;
+}
+
+hipError_t sweep_launch(const SweepArgs& host, const SweepArgs* dev, const SweepPlan& plan,
+                        hipStream_t st) {
+    KernelFn f = kernel_for(host.x.xtype, plan.chunks);
     if (!f) return hipErrorInvalidValue;
-    SweepArgs a = a0;
-    a.gp = plan.gp;
-    a.gz = (a.mode & kModeZ) ? plan.gz : 0u;
-    a.zgroups = (a.gz + kZGroup - 1) / kZGroup;
-    void* args[] = {&a};
-    return hipLaunchKernel(reinterpret_cast<const void*>(f), dim3(a.gp + a.gz), dim3(kThreads), args,
-                           0, st);
+    void* args[] = {&dev};
+    return hipLaunchKernel(reinterpret_cast<const void*>(f), dim3(host.gp + host.gz), dim3(kThreads),
+                           args, 0, st);
 }
 
 }  // namespace hsp

@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "HSP_OK", -1: "HSP_EINVAL", -2: "HSP_ENOMEM", -3: "HSP_EHIP",
 EXPORTS = ["hsp_default_options", "hsp_max_p", "hsp_create", "hsp_sweep", "hsp_sync", "hsp_draws",
            "hsp_destroy", "hsp_last_error", "hsp_get_state", "hsp_set_state", "hsp_step",
            "hsp_get_debug", "hsp_get_gram", "hsp_get_counters", "hsp_set_timing",
-           "hsp_get_timing", "hsp_philox", "hsp_set_phase_trace", "hsp_get_phase_trace"]
+           "hsp_get_timing", "hsp_philox", "hsp_set_phase_trace", "hsp_get_phase_trace",
+           "hsp_tile_schedule"]
 
 
 class hsp_options(C.Structure):
@@ -80,6 +81,8 @@ def load():
     L.hsp_set_phase_trace.argtypes = [vp, i32]; L.hsp_set_phase_trace.restype = st
     L.hsp_get_phase_trace.argtypes = [vp, vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(d)]
     L.hsp_get_phase_trace.restype = st
+    L.hsp_tile_schedule.argtypes = [i64, i64, vp, i64, vp, C.POINTER(i64)]
+    L.hsp_tile_schedule.restype = st
     _lib = L
     return L
 
@@ -189,6 +192,18 @@ def hsp_philox(seed, ctr):
     out = np.zeros_like(ctr)
     _check(load().hsp_philox(seed, _hp(ctr), ctr.shape[0], _hp(out)))
     return out
+
+
+def hsp_tile_schedule(nt, gp):
+    """Per-block task lists of the tiled factorisation: (tasks, offsets)."""
+    n = C.c_int64()
+    st = load().hsp_tile_schedule(nt, gp, None, 0, None, C.byref(n))
+    if st not in (HSP_OK, HSP_ERANGE):
+        _check(st)
+    tasks = np.zeros(max(n.value, 1), np.uint32)
+    off = np.zeros(gp + 1, np.uint32)
+    _check(load().hsp_tile_schedule(nt, gp, _hp(tasks), tasks.size, _hp(off), C.byref(n)))
+    return tasks[: n.value], off
 
 
 def hsp_set_phase_trace(h, enable):
