@@ -173,14 +173,16 @@ hsp_status hsp_get_timing(hsp_state* s, double* zpass_ms, double* sweep_ms, int6
 
 /* Diagnostics: when enabled, every launch of the sweep kernel stores, per
  * block of its p-side group, a timestamp at the start (slot 0); then, in
- * order from slot 1 up to slot 191, one per event: each group barrier
- * passed, and for each factorisation task (p > 128) the moment its inputs
- * were ready and the moment it was done; from slot 192, five records of 12
- * slots for the diagonal tiles the block factored (loaded, after each of the
- * four panels and their updates, inverted, stored); and in the last slot the
- * moment the z pass was seen complete.  hsp_get_phase_trace copies
- * group_blocks x slots uint64 values of the last launch; ticks_per_us
- * converts them.  Enabling drops the captured graph. */
+ * order from slot 1 up to slot 447, one value per event: a timestamp for each
+ * group barrier passed, and for each factorisation task (p > 128) its index + 1
+ * in the task lists of hsp_tile_schedule plus one, then timestamps of when its
+ * inputs were ready, its input tiles were loaded and it was done; from slot
+ * 448, five records of 12 slots for the diagonal tiles the block factored
+ * (loaded, after each of the four panels and their updates, stored); and in
+ * the last slot the moment the z pass was seen complete.
+ * hsp_get_phase_trace copies group_blocks x slots uint64 values of the last
+ * launch; ticks_per_us converts the timestamps.  Enabling drops the captured
+ * graph. */
 hsp_status hsp_set_phase_trace(hsp_state* s, int32_t enable);
 hsp_status hsp_get_phase_trace(hsp_state* s, uint64_t* out, int64_t* group_blocks, int64_t* slots,
                                double* ticks_per_us);
@@ -188,16 +190,19 @@ hsp_status hsp_get_phase_trace(hsp_state* s, uint64_t* out, int64_t* group_block
 /* The factorisation schedule for p > 128 (host only, no device work): the
  * Cholesky factorisation of Q by 64 x 64 tiles (Section 5, beta step iii),
  * with the same row operations applied to an identity block, is split into
- * tile tasks that the p-side blocks of the sweep kernel run from static
- * per-block lists.  nt = ceil(p / 64) tiles per side, gp blocks.
+ * tile tasks that the p-side blocks of the sweep kernel run.  nt =
+ * ceil(p / 64) tiles per side, gp blocks.
  * Task code: type (bits 0-1: 0 factor a diagonal tile, 1 triangular solve of
- * a tile of the block row, 2 tile update) | part (bit 2: 0 U, 1 L^-1) | step k
- * (bits 3-9) | tile row i (bits 10-16) | tile column j (bits 17-23).
- * tasks (capacity cap) receives every block's list in order, off (gp + 1
- * entries) the offsets of block b's list; *n_tasks the total count (also when
- * cap is too small, then HSP_ERANGE).  Errors: HSP_EINVAL if nt < 1,
- * nt > 64 or gp < 1.  Test hook for the schedule's coverage and deadlock
- * freedom. */
+ * a tile of the block row, 2 tile update, 3 the next diagonal tile's solve,
+ * update and factorisation in one block) | part (bit 2: 0 U, 1 L^-1) | step
+ * k (bits 3-9) | tile row i (bits 10-16) | tile column j (bits 17-23).
+ * With gp = 1, off[0..1] delimits block 0's list; with gp > 1, off[0..1]
+ * delimits block 0's list (the critical chain) and off[1..2] the shared
+ * queue that the other blocks claim tasks from, in order.  tasks (capacity
+ * cap) receives the lists, off (3 entries) their bounds, *n_tasks the total
+ * count (also when cap is too small, then HSP_ERANGE).  Errors: HSP_EINVAL
+ * if nt < 1, nt > 64 or gp < 1.  Test hook for the schedule's coverage and
+ * deadlock freedom. */
 hsp_status hsp_tile_schedule(int64_t nt, int64_t gp, uint32_t* tasks, int64_t cap, uint32_t* off,
                              int64_t* n_tasks);
 

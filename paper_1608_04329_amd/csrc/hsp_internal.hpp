@@ -13,7 +13,10 @@ constexpr uint32_t kMaxRounds = 2048;  // 4096 truncated-normal proposals per ro
 constexpr int kThreads = 256;          // threads per block of the sweep kernel
 constexpr int kTile = 64;              // p-side tile edge
 constexpr int kSmallP = 128;           // p up to this runs the one-block p-side path
-constexpr int kMaxGroup = 32;          // most blocks of the p-side group
+#ifndef HSP_MAX_GROUP
+#define HSP_MAX_GROUP 32
+#endif
+constexpr int kMaxGroup = HSP_MAX_GROUP;  // most blocks of the p-side group
 constexpr int kZGroup = 16;            // z-pass blocks whose partials one block sums
 // LDS of one sweep-kernel block: two 64 x 66 float64 tiles (67,584 bytes; rows
 // 16-byte aligned).  The same buffer holds the z pass's reduction segment and
@@ -29,7 +32,7 @@ struct Ctrl {
     uint32_t max_attempts;      // most proposals any row needed
     unsigned long long clamps;  // lambda rates clamped to DBL_MIN
     int32_t chol_info;          // first non-positive pivot (1-based), 0 if none
-    uint32_t pad;
+    uint32_t task_next;         // next factorisation task of the shared queue (zero between launches)
     unsigned long long bar_count;  // arrivals at p-side group barriers (monotonic)
     unsigned long long bar_epoch;  // bar_count when the current launch started
     unsigned long long z_count;    // z-pass blocks finished (monotonic)
@@ -106,25 +109,28 @@ struct SweepArgs {
     uint32_t* ver;           // tile path: 2 x nt x nt tile version counters (zero between launches)
 };
 
-// Diagnostic trace per group block: slot 0 = start, slots 1.. one timestamp per
-// event in order (group barriers; per factorisation task: inputs ready, done),
-// then kTraceRecs records of kTraceRec slots for the diagonal tiles the block
-// factored (loaded, panels, inverse, stored), and the last slot = z pass seen
-// complete.
-constexpr int kTraceSlots = 256;
-constexpr int kTraceSeq = 192;
+// Diagnostic trace per group block: slot 0 = start, slots 1.. one value per
+// event in order (group barriers: a timestamp; per factorisation task: its
+// index in the task array, then timestamps when its inputs were ready, loaded
+// and done), then kTraceRecs records of kTraceRec slots for the diagonal tiles
+// the block factored (loaded, panels, stored), and the last slot = z pass
+// seen complete.
+constexpr int kTraceSlots = 512;
+constexpr int kTraceSeq = 448;
 constexpr int kTraceRec = 12;
 constexpr int kTraceRecs = 5;
 
 // ---- tasks of the tiled factorisation (p > 128) ----------------------------------
-enum : uint32_t { kTaskPotrf = 0u, kTaskTrsm = 1u, kTaskGemm = 2u };
+enum : uint32_t { kTaskPotrf = 0u, kTaskTrsm = 1u, kTaskGemm = 2u, kTaskPanel = 3u };
 // type (2 bits) | part (0: U, 1: L^-1) | step k | tile row i | tile column j (7 bits each)
 __host__ __device__ constexpr uint32_t task_code(uint32_t type, uint32_t part, uint32_t k, uint32_t i,
                                                  uint32_t j) {
     return type | part << 2 | k << 3 | i << 10 | j << 17;
 }
-// Per-block task lists of the factorisation of [Q | I] over gp blocks
-// (schedule.cpp): tasks[off[b] .. off[b + 1]) are block b's, in order.
+// Task lists of the factorisation of [Q | I] for a group of gp blocks
+// (schedule.cpp): with gp = 1 one list, tasks[off[0] .. off[1]), run in order by
+// block 0; with gp > 1 block 0's chain list tasks[off[0] .. off[1]) and the
+// shared queue tasks[off[1] .. off[2]) the other blocks claim in order.
 void chol_schedule(uint32_t nt, uint32_t gp, std::vector<uint32_t>* tasks,
                    std::vector<uint32_t>* off);
 

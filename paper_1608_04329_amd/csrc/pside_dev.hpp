@@ -73,9 +73,12 @@ __device__ __forceinline__ void wait_count(unsigned long long* ctr, unsigned lon
     }
 }
 
-// Thread 0: next trace timestamp (diagnostics only).
+// Thread 0: next trace timestamp, or a given value (diagnostics only).
 __device__ __forceinline__ void stamp(Group& g) {
     if (g.trace && threadIdx.x == 0 && g.slot + 1 < (uint32_t)kTraceSeq) g.trace[++g.slot] = wall_clock64();
+}
+__device__ __forceinline__ void stamp_value(Group& g, uint64_t v) {
+    if (g.trace && threadIdx.x == 0 && g.slot + 1 < (uint32_t)kTraceSeq) g.trace[++g.slot] = v;
 }
 
 // Thread 0: timestamp into slot s of a diagonal-factorisation record (or none).
@@ -99,6 +102,21 @@ __device__ __forceinline__ bool wait_ver(uint32_t* ver, uint32_t need, Ctrl* ctr
         __builtin_amdgcn_s_sleep(1);
     }
     return true;
+}
+
+// Make this block's global stores visible device-wide, then set *ver = val
+// (and *ver2 = val2):
+// every wave waits for its own stores, and one thread writes the cache back
+// and publishes (a release fence per block, not per wave).
+__device__ __forceinline__ void publish(uint32_t* ver, uint32_t val, uint32_t* ver2 = nullptr,
+                                        uint32_t val2 = 0) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_store(ver, val, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (ver2) __hip_atomic_store(ver2, val2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 __device__ __forceinline__ void group_sync(Group& g) {
@@ -397,9 +415,6 @@ __device__ void small_path(const SweepArgs& a, Group& g, uint32_t k, double* lds
 // leading dimension P: Gp holds G with an identity block on the padding, so
 // the factor, L^-1 and Q^-1 carry an identity block there too and no tile
 // ever needs a bounds check.
-#ifndef HSP_TILE_MFMA
-#define HSP_TILE_MFMA 1
-#endif
 typedef double Tile[kTile][kTileLd];
 
 __device__ __forceinline__ uint32_t padded(uint32_t p) { return (p + kTile - 1) / kTile * kTile; }
@@ -447,26 +462,7 @@ __device__ __forceinline__ void load_tiles(Tile& S, const double* MS, uint32_t r
     }
 }
 
-// acc[t][u] = sum_q S[q][ty*4+t] * T[q][tx*4+u]  (a 64 x 64 x 64 product S^T T).
-// Rows are 16-byte aligned: each thread reads its 4 + 4 operands per q with
-// four 16-byte LDS loads.
-__device__ __forceinline__ void gemm_tn(const Tile& S, const Tile& T, double (&acc)[4][4]) {
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll 4
-    for (int q = 0; q < kTile; ++q) {
-        const double2* sp = reinterpret_cast<const double2*>(&S[q][ty * 4]);
-        const double2* tp = reinterpret_cast<const double2*>(&T[q][tx * 4]);
-        const double2 s01 = sp[0], s23 = sp[1], v01 = tp[0], v23 = tp[1];
-        const double s[4] = {s01.x, s01.y, s23.x, s23.y};
-        const double v[4] = {v01.x, v01.y, v23.x, v23.y};
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[t][u] = fma(s[t], v[u], acc[t][u]);
-    }
-}
-
-// ---- the same 64 x 64 x 64 products on the FP64 matrix cores ----------------
+// ---- 64 x 64 x 64 tile products on the FP64 matrix cores ----------------------
 // v_mfma_f64_16x16x4f64 computes D(16x16) += A(16x4) B(4x16); lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[l / 16 + 4 r][l % 16]
 // in its r-th result.  Wave w owns the 32 x 32 quadrant at rows 32 (w / 2),
@@ -477,7 +473,9 @@ struct MAcc {
     Acc4 v[2][2];
 };
 
-__device__ __forceinline__ void gemm_tn_mfma(const Tile& S, const Tile& T, MAcc& acc) {
+// acc = S^T T, or S T when TA (S read transposed: its rows are the product's rows).
+template <bool TA = false>
+__device__ __forceinline__ void gemm_tn(const Tile& S, const Tile& T, MAcc& acc) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i0 = 32 * (wave >> 1), j0 = 32 * (wave & 1);
     const int kr = lane >> 4, cc = lane & 15;
@@ -487,7 +485,8 @@ __device__ __forceinline__ void gemm_tn_mfma(const Tile& S, const Tile& T, MAcc&
         for (int bj = 0; bj < 2; ++bj) acc.v[bi][bj] = Acc4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
     for (int q0 = 0; q0 < kTile; q0 += 4) {
-        const double a0 = S[q0 + kr][i0 + cc], a1 = S[q0 + kr][i0 + 16 + cc];
+        const double a0 = TA ? S[i0 + cc][q0 + kr] : S[q0 + kr][i0 + cc];
+        const double a1 = TA ? S[i0 + 16 + cc][q0 + kr] : S[q0 + kr][i0 + 16 + cc];
         const double b0 = T[q0 + kr][j0 + cc], b1 = T[q0 + kr][j0 + 16 + cc];
         acc.v[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.v[0][0], 0, 0, 0);
         acc.v[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.v[0][1], 0, 0, 0);
@@ -496,12 +495,44 @@ __device__ __forceinline__ void gemm_tn_mfma(const Tile& S, const Tile& T, MAcc&
     }
 }
 
-// store_tile for the matrix-core layout: sixteen values per lane, each a
-// 128-byte row segment across 16 lanes.
-__device__ __forceinline__ void store_tile_m(double* M, uint32_t P, uint32_t r0, uint32_t c0,
-                                             const MAcc& acc, double sign, const double* src,
-                                             bool add_diag, double tau, const double* lam,
-                                             uint32_t p) {
+// The matrix-core layout of a 64 x 64 tile at (r0, c0) of M: lane l of wave w
+// holds rows r0 + 32 (w / 2) + 16 bi + l / 16 + 4 r, column c0 + 32 (w % 2) +
+// 16 bj + l % 16; each group of 16 lanes covers a 128-byte row segment.
+struct MTile {
+    double v[2][2][4];
+};
+
+// Load a tile in that layout (zeros for a null M), with tau * lam added on
+// Q's diagonal when add_diag.  Issued before a product, the loads overlap it.
+__device__ __forceinline__ void load_tile_m(MTile& o, const double* M, uint32_t P, uint32_t r0,
+                                            uint32_t c0, bool add_diag, double tau, const double* lam,
+                                            uint32_t p) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t ri = r0 + 32 * (wave >> 1) + (lane >> 4);
+    const uint32_t cj = c0 + 32 * (wave & 1) + (lane & 15);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                o.v[bi][bj][r] = M ? M[(size_t)(ri + 16 * bi + 4 * r) * P + cj + 16 * bj] : 0.0;
+    if (add_diag) {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t gi = ri + 16 * bi + 4 * r, gj = cj + 16 * bj;
+                    if (gi == gj && gi < p) o.v[bi][bj][r] += tau * lam[gi];
+                }
+    }
+}
+
+// M(r0.., c0..) = old + sign * acc, sixteen stores back to back.
+__device__ __forceinline__ void put_tile_m(double* M, uint32_t P, uint32_t r0, uint32_t c0,
+                                           const MAcc& acc, double sign, const MTile& old) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t ri = r0 + 32 * (wave >> 1) + (lane >> 4);
     const uint32_t cj = c0 + 32 * (wave & 1) + (lane & 15);
@@ -511,124 +542,28 @@ __device__ __forceinline__ void store_tile_m(double* M, uint32_t P, uint32_t r0,
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                out[bi][bj][r] = src ? src[(size_t)(ri + 16 * bi + 4 * r) * P + cj + 16 * bj] : 0.0;
-    if (add_diag) {
+            for (int r = 0; r < 4; ++r) out[bi][bj][r] = fma(sign, acc.v[bi][bj][r], old.v[bi][bj][r]);
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const uint32_t gi = ri + 16 * bi + 4 * r, gj = cj + 16 * bj;
-                    if (gi == gj && gi < p) out[bi][bj][r] += tau * lam[gi];
-                }
-    }
+            for (int r = 0; r < 4; ++r) M[(size_t)(ri + 16 * bi + 4 * r) * P + cj + 16 * bj] = out[bi][bj][r];
+}
+
+// X = old + sign * acc in LDS (the matrix-core layout, X's own rows and columns).
+__device__ __forceinline__ void acc_to_lds(Tile& X, const MAcc& acc, double sign, const MTile& old) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ri = 32 * (wave >> 1) + (lane >> 4), cj = 32 * (wave & 1) + (lane & 15);
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                out[bi][bj][r] = fma(sign, acc.v[bi][bj][r], out[bi][bj][r]);
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                M[(size_t)(ri + 16 * bi + 4 * r) * P + cj + 16 * bj] = out[bi][bj][r];
+                X[ri + 16 * bi + 4 * r][cj + 16 * bj] = fma(sign, acc.v[bi][bj][r], old.v[bi][bj][r]);
 }
 
-__device__ __forceinline__ void zero_acc(double (&acc)[4][4]) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[t][u] = 0.0;
-}
-
-// M(r0.., c0..) = sign * acc + (old from src, with tau * lam on Q's diagonal if
-// add_diag).  Loads, arithmetic, then the 16 stores back to back.
-__device__ __forceinline__ void store_tile(double* M, uint32_t P, uint32_t r0, uint32_t c0,
-                                           const double (&acc)[4][4], double sign, const double* src,
-                                           bool add_diag, double tau, const double* lam, uint32_t p) {
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const size_t base = (size_t)(r0 + ty * 4) * P + c0 + tx * 4;
-    double out[4][4];
-    if (src) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) out[t][u] = src[base + (size_t)t * P + u];
-    } else {
-        zero_acc(out);
-    }
-    if (add_diag) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t gi = r0 + ty * 4 + t, gj = c0 + tx * 4 + u;
-                if (gi == gj && gi < p) out[t][u] += tau * lam[gi];
-            }
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) out[t][u] = fma(sign, acc[t][u], out[t][u]);
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) M[base + (size_t)t * P + u] = out[t][u];
-}
-
-// Inverse of the upper-triangular 64 x 64 U (in S) into T, by recursive
-// doubling: T starts as diag(1/U_ii); for b = 1, 2, ..., 32 every diagonal
-// 2b-block [U1 U12; 0 U2] gets W12 = -W1 (U12 W2).  U12 W2 is parked in the
-// (otherwise zero) lower-left b x b block and cleared at the end.  The inner
-// loops have compile-time length, so their LDS reads issue together.
-template <int LB>
-__device__ __forceinline__ void inverse_level(const Tile& S, Tile& T) {
-    constexpr int b = 1 << LB;
-    constexpr int n = (kTile / (2 * b)) * b * b;  // entries of all the b x b products
-    for (int e2 = threadIdx.x; e2 < n; e2 += kThreads) {
-        const int m = e2 >> (2 * LB), r = (e2 >> LB) & (b - 1), c = e2 & (b - 1);
-        const int o = 2 * b * m;
-        double x = 0.0;
-#pragma unroll
-        for (int q = 0; q < b; ++q) {
-            const double w = q <= c ? T[o + b + q][o + b + c] : 0.0;  // W2 is upper
-            x = fma(S[o + r][o + b + q], w, x);
-        }
-        T[o + b + r][o + c] = x;
-    }
-    __syncthreads();
-    for (int e2 = threadIdx.x; e2 < n; e2 += kThreads) {
-        const int m = e2 >> (2 * LB), r = (e2 >> LB) & (b - 1), c = e2 & (b - 1);
-        const int o = 2 * b * m;
-        double w = 0.0;
-#pragma unroll
-        for (int q = 0; q < b; ++q) {
-            const double v = q >= r ? T[o + r][o + q] : 0.0;  // W1 is upper
-            w = fma(v, T[o + b + q][o + c], w);
-        }
-        T[o + r][o + b + c] = -w;
-    }
-    __syncthreads();
-}
-
-// Factor a 64 x 64 diagonal block (upper part of S, zeros below; identity
-// beyond the matrix edge) into U (upper, in S) and its inverse (in T).
-//
-// Four row panels of 16.  For each, wave 0 eliminates the panel in registers:
-// lane j holds the panel's 16 entries of column j; at step c the pivot is
-// lane (r0 + c)'s entry c (a scalar read of one lane), row c is scaled by
-// 1/sqrt(pivot), and the panel rows below lose U[c][i] times it (U[c][i] read
-// from lane r0 + i).  That is
-// both the 16 x 16 factorisation and the solve of the panel's columns to the
-// right.  Then every wave subtracts the panel's contribution from the
-// trailing block.  Eight barriers.  Returns false on a non-positive pivot
-// (uniformly: the flag goes through LDS).
 __device__ __forceinline__ double rdlane(double v, int l) {
     const unsigned long long u = (unsigned long long)__double_as_longlong(v);
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
@@ -636,81 +571,112 @@ __device__ __forceinline__ double rdlane(double v, int l) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// 1 / sqrt(d) for d > 0: the hardware estimate and one Newton step.
+__device__ __forceinline__ double rsqrt_nr(double d) {
+    const double y = __builtin_amdgcn_rsq(d);
+    const double e = fma(-d * y, y, 1.0);  // 1 - d y^2
+    return fma(0.5 * y, e, y);
+}
+
+// Factor a 64 x 64 diagonal block: S holds its upper part (zeros below,
+// identity beyond the matrix edge); on return S = U (upper) and T = U^-T
+// (lower), i.e. the factorisation of [S | I] by row operations.
+//
+// Four row panels of 16.  For each, wave 0 eliminates the panel in registers,
+// columns across the lanes: at step c the pivot is lane (r0 + c)'s entry c,
+// row c is scaled by 1/sqrt(pivot) and every later panel row i loses U[c][i]
+// times it (U[c][i] read from lane r0 + i), in the S part and in the identity
+// part alike.  That factors the panel's diagonal block and solves its other
+// columns at once.  Then all four waves subtract the panel's rank-16
+// contribution from the rows below on the matrix cores, as 16 x 16 blocks:
+// S(I, J) -= U(P, I)^T U(P, J) for P < I <= J, and T(I, J) -= U(P, I)^T T(P, J)
+// for J <= P < I.  Returns false on a non-positive pivot (uniformly: the flag
+// goes through LDS).
 __device__ bool factor_diag(Tile& S, Tile& T, uint64_t* rec) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double* flag = &T[kTile - 1][kTile];  // padding corner, not part of the tile
+    for (int e = threadIdx.x; e < kTile * kTile; e += kThreads) T[e / kTile][e % kTile] = e / kTile == e % kTile ? 1.0 : 0.0;
+    __syncthreads();
 #pragma unroll
     for (int P = 0; P < 4; ++P) {
         const int r0 = 16 * P;
         if (wave == 0) {
-            double a[16];
+            double a[16], w[16];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) a[c] = S[r0 + c][lane];
+            for (int c = 0; c < 16; ++c) {
+                a[c] = S[r0 + c][lane];
+                w[c] = T[r0 + c][lane];
+            }
             bool ok = true;
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
                 const double d = rdlane(a[c], r0 + c);
                 ok = ok && (d > 0.0);
-                const double rs = 1.0 / sqrt(d);
+                const double rs = rsqrt_nr(d);
                 a[c] = lane == r0 + c ? d * rs : a[c] * rs;
+                w[c] *= rs;
 #pragma unroll
-                for (int i = c + 1; i < 16; ++i) a[i] = fma(-rdlane(a[c], r0 + i), a[c], a[i]);
+                for (int i = c + 1; i < 16; ++i) {
+                    const double m = rdlane(a[c], r0 + i);
+                    a[i] = fma(-m, a[c], a[i]);
+                    w[i] = fma(-m, w[c], w[i]);
+                }
             }
 #pragma unroll
-            for (int c = 0; c < 16; ++c) S[r0 + c][lane] = lane >= r0 + c ? a[c] : 0.0;
+            for (int c = 0; c < 16; ++c) {
+                S[r0 + c][lane] = lane >= r0 + c ? a[c] : 0.0;
+                T[r0 + c][lane] = w[c];
+            }
             if (lane == 0) *flag = ok ? 0.0 : 1.0;
         }
         __syncthreads();
         stamp_at(rec, 1 + 2 * P);
         if (*flag != 0.0) return false;
-        // trailing update: S[i][j] -= sum_c S[r0+c][i] S[r0+c][j], r0+16 <= i <= j
-        constexpr int m0 = 0;
-        (void)m0;
-        const int m = 48 - r0;
-        for (int e = threadIdx.x; e < m * m; e += kThreads) {
-            const int i = r0 + 16 + e / m, j = r0 + 16 + e % m;
-            if (j >= i) {
-                double x = S[i][j];
+        if (P < 3) {
+            // blocks below the panel: S part (I, J), P < I <= J <= 3, then the
+            // T part (I, J), I > P, J <= P; wave w takes blocks w, w + 4, ...
+            const int nS = (3 - P) * (4 - P) / 2, nT = (3 - P) * (P + 1);
+            const int kr = lane >> 4, cc = lane & 15;
+            for (int blk = wave; blk < nS + nT; blk += kThreads / kWave) {
+                int I, J;
+                bool spart = blk < nS;
+                if (spart) {
+                    int idx = blk;
+                    I = P + 1;
+                    while (idx >= 4 - I) {
+                        idx -= 4 - I;
+                        ++I;
+                    }
+                    J = I + idx;
+                } else {
+                    const int t2 = blk - nS;
+                    I = P + 1 + t2 / (P + 1);
+                    J = t2 % (P + 1);
+                }
+                Tile& B = spart ? S : T;
+                Acc4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int c = 0; c < 16; ++c) x = fma(-S[r0 + c][i], S[r0 + c][j], x);
-                S[i][j] = x;
+                for (int kk = 0; kk < 4; ++kk) {
+                    const double x = S[r0 + 4 * kk + kr][16 * I + cc];
+                    const double y = B[r0 + 4 * kk + kr][16 * J + cc];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) B[16 * I + kr + 4 * r][16 * J + cc] -= acc[r];
             }
         }
         __syncthreads();
         stamp_at(rec, 2 + 2 * P);
     }
-    // T = U^-1
-    for (int e = threadIdx.x; e < kTile * kTile; e += kThreads) {
-        const int r = e / kTile, c = e % kTile;
-        T[r][c] = r == c ? 1.0 / S[r][r] : 0.0;
-    }
-    __syncthreads();
-    inverse_level<0>(S, T);
-    inverse_level<1>(S, T);
-    inverse_level<2>(S, T);
-    inverse_level<3>(S, T);
-    inverse_level<4>(S, T);
-    inverse_level<5>(S, T);
-    for (int e = threadIdx.x; e < kTile * kTile; e += kThreads) {
-        const int r = e / kTile, c = e % kTile;
-        if (c < r) T[r][c] = 0.0;
-    }
-    __syncthreads();
     stamp_at(rec, 9);
     return true;
 }
 
-// Factor diagonal block kb: load it (from Gp + tau Lambda for kb = 0), factor,
-// store U_kk into A, its inverse D into Dinv[kb] and D^T = L^-1_kk into Linv.
-// Reports a failed pivot.
-__device__ void diag_block(const SweepArgs& a, uint32_t kb, double tau, Tile& S, Tile& T,
-                           uint64_t* rec) {
-    const uint32_t p = a.x.p, P = padded(p), k0 = kb * kTile;
-    load_tile(S, kb == 0 ? a.Gp : a.A, P, k0, k0, kb == 0, tau, a.lam_m2, p);
-    __syncthreads();
-    for (int e = threadIdx.x; e < kTile * kTile; e += kThreads)
-        if (e % kTile < e / kTile) S[e / kTile][e % kTile] = 0.0;
-    __syncthreads();
+// Factor diagonal block kb held in S (its upper part; the rest is not read):
+// store U_kk into A, D = U_kk^-1 into Dinv[kb] and D^T = L^-1_kk into Linv.
+// Reports a failed pivot.  On return S = U_kk and T = D^T.
+__device__ void diag_factor(const SweepArgs& a, uint32_t kb, Tile& S, Tile& T, uint64_t* rec) {
+    const uint32_t P = padded(a.x.p), k0 = kb * kTile;
     stamp_at(rec, 0);
     if (factor_diag(S, T, rec)) {
         double* D = a.Dinv + (size_t)kb * kTile * kTile;
@@ -719,8 +685,8 @@ __device__ void diag_block(const SweepArgs& a, uint32_t kb, double tau, Tile& S,
         for (int q = 0; q < 16; ++q) {
             const int r = rb + 4 * q;
             a.A[(size_t)(k0 + r) * P + k0 + c] = S[r][c];
-            D[r * kTile + c] = T[r][c];
-            a.Linv[(size_t)(k0 + r) * P + k0 + c] = T[c][r];
+            D[r * kTile + c] = T[c][r];
+            a.Linv[(size_t)(k0 + r) * P + k0 + c] = T[r][c];
         }
     } else if (threadIdx.x == 0) {
         atomicOr(&a.ctrl->err, kErrNotPD);
@@ -728,27 +694,6 @@ __device__ void diag_block(const SweepArgs& a, uint32_t kb, double tau, Tile& S,
     }
     __syncthreads();
     stamp_at(rec, 10);
-}
-
-// Decode update tile t of step kb: A-part tiles (i, j), kb < i <= j, come first,
-// then L^-1-part tiles (i, j), i > kb, j <= kb.
-__device__ __forceinline__ bool update_tile(uint32_t t, uint32_t kb, uint32_t nt, uint32_t* ib,
-                                            uint32_t* jb) {
-    const uint32_t m = nt - kb - 1, nA = m * (m + 1) / 2;
-    if (t < nA) {
-        uint32_t idx = t, r = 0;
-        while (idx >= m - r) {
-            idx -= m - r;
-            ++r;
-        }
-        *ib = kb + 1 + r;
-        *jb = *ib + idx;
-        return true;
-    }
-    const uint32_t t2 = t - nA;
-    *ib = kb + 1 + t2 / (kb + 1);
-    *jb = t2 % (kb + 1);
-    return false;
 }
 
 // Run block `rank`'s list of factorisation tasks.  Tile versions: U tile
@@ -761,15 +706,32 @@ __device__ bool run_tasks(const SweepArgs& a, Group& g, uint32_t rank, double ta
     const uint32_t p = a.x.p, P = padded(p), nt = P / kTile;
     uint32_t* vU = a.ver;
     uint32_t* vL = a.ver + nt * nt;
-    const uint32_t n0 = a.task_off[rank], n1 = a.task_off[rank + 1];
-    for (uint32_t n = n0; n < n1; ++n) {
+    // Block 0 (or a group of one) runs its own list; the others claim tasks
+    // from the shared queue in order, each reserving its next task when it
+    // starts one.  The claimed index travels to the block through LDS.
+    const bool queue = g.size > 1 && rank > 0;
+    const uint32_t n0 = queue ? a.task_off[1] : 0u, n1 = queue ? a.task_off[2] : a.task_off[1];
+    double* next_lds = &T[kTile - 2][kTile];  // padding, not part of the tile
+    uint32_t n = n0;
+    if (queue) {
+        if (threadIdx.x == 0) *next_lds = (double)atomicAdd(&a.ctrl->task_next, 1u);
+        __syncthreads();
+        n = n0 + (uint32_t)*next_lds;
+        __syncthreads();
+    }
+    while (n < n1) {
         const uint32_t code = a.tasks[n];
         const uint32_t type = code & 3u, part = (code >> 2) & 1u, kb = (code >> 3) & 127u,
                        ib = (code >> 10) & 127u, jb = (code >> 17) & 127u;
+        uint32_t reserved = 0;
         if (threadIdx.x == 0) {
+            if (queue) reserved = atomicAdd(&a.ctrl->task_next, 1u);
             bool w = true;
             if (type == kTaskPotrf) {
                 w = wait_ver(&vU[kb * nt + kb], kb, a.ctrl, g.timeout);
+            } else if (type == kTaskPanel) {
+                w = wait_ver(&vU[(kb - 1) * nt + kb], kb - 1, a.ctrl, g.timeout) &&
+                    wait_ver(&vU[kb * nt + kb], kb - 1, a.ctrl, g.timeout);
             } else if (type == kTaskTrsm) {
                 w = wait_ver(&vU[kb * nt + kb], kb + 1, a.ctrl, g.timeout) &&
                     (part == 0 ? wait_ver(&vU[kb * nt + jb], kb, a.ctrl, g.timeout)
@@ -785,25 +747,53 @@ __device__ bool run_tasks(const SweepArgs& a, Group& g, uint32_t rank, double ta
             __threadfence();
         }
         __syncthreads();
+        stamp_value(g, n + 1u);
         stamp(g);
         if (*flag != 0.0) return false;
         const uint32_t k0 = kb * kTile;
-        uint32_t* out = nullptr;
+        uint32_t* out = nullptr;   // version published when the task is done
+        uint32_t* out2 = nullptr;  // a diagonal L^-1 tile, final at version 1
         uint32_t val = 0;
-        if (type == kTaskPotrf) {
+        if (type == kTaskPotrf || type == kTaskPanel) {
             uint64_t* rec = nullptr;
             if (g.trace && g.npotrf < (uint32_t)kTraceRecs) rec = g.trace + kTraceSeq + kTraceRec * g.npotrf;
             g.npotrf++;
-            diag_block(a, kb, tau, S, T, rec);
+            if (type == kTaskPotrf) {
+                load_tile(S, kb == 0 ? a.Gp : a.A, P, k0, k0, kb == 0, tau, a.lam_m2, p);
+                __syncthreads();
+                stamp(g);
+            } else {
+                // U_{k-1,k} = D_{k-1}^T A_{k-1,k} with D_{k-1}^T still in T, then
+                // A_kk -= U_{k-1,k}^T U_{k-1,k}, all in this block
+                const uint32_t km = kb - 1, r1 = km * kTile;
+                const double* src = km == 0 ? a.Gp : a.A;
+                MTile dg;
+                load_tile_m(dg, src, P, k0, k0, km == 0, tau, a.lam_m2, p);
+                load_tile(S, src, P, r1, k0, false, 0.0, nullptr, p);
+                __syncthreads();
+                stamp(g);
+                MAcc acc;
+                gemm_tn<true>(T, S, acc);
+                MTile zero;
+                load_tile_m(zero, nullptr, P, 0, 0, false, 0.0, nullptr, p);
+                put_tile_m(a.A, P, r1, k0, acc, 1.0, zero);
+                __syncthreads();
+                acc_to_lds(S, acc, 1.0, zero);
+                publish(&vU[km * nt + kb], kb);
+                gemm_tn(S, S, acc);
+                __syncthreads();
+                acc_to_lds(S, acc, -1.0, dg);
+                __syncthreads();
+            }
+            diag_factor(a, kb, S, T, rec);
             if (threadIdx.x == 0 &&
                 (__hip_atomic_load(&a.ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrNotPD))
                 *flag = 1.0;
             __syncthreads();
             if (*flag != 0.0) return false;
-            if (threadIdx.x == 0)
-                __hip_atomic_store(&vL[kb * nt + kb], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             out = &vU[kb * nt + kb];
             val = kb + 1;
+            out2 = &vL[kb * nt + kb];
         } else if (type == kTaskTrsm) {
             // row kb times D = U_kk^-1: X_kj = D^T X_kj
             const double* Dk = a.Dinv + (size_t)kb * kTile * kTile;
@@ -822,49 +812,37 @@ __device__ bool run_tasks(const SweepArgs& a, Group& g, uint32_t rank, double ta
                 T[rb + 4 * q][c] = x[q];
             }
             __syncthreads();
-#if HSP_TILE_MFMA
+            stamp(g);
             MAcc acc;
-            gemm_tn_mfma(S, T, acc);
-            store_tile_m(part == 0 ? a.A : a.Linv, P, k0, j0, acc, 1.0, nullptr, false, 0.0, nullptr, p);
-#else
-            double acc[4][4];
-            zero_acc(acc);
             gemm_tn(S, T, acc);
-            store_tile(part == 0 ? a.A : a.Linv, P, k0, j0, acc, 1.0, nullptr, false, 0.0, nullptr, p);
-#endif
+            MTile zero;
+            load_tile_m(zero, nullptr, P, 0, 0, false, 0.0, nullptr, p);
+            put_tile_m(part == 0 ? a.A : a.Linv, P, k0, j0, acc, 1.0, zero);
             out = part == 0 ? &vU[kb * nt + jb] : &vL[kb * nt + jb];
             val = part == 0 ? kb + 1 : kb - jb + 1;
         } else {
-            // A_ij -= U_ki^T U_kj  or  L^-1_ij -= U_ki^T L^-1_kj
+            // A_ij -= U_ki^T U_kj  or  L^-1_ij -= U_ki^T L^-1_kj; the three
+            // tiles' loads are in flight together
+            MTile old;
+            if (part == 0)
+                load_tile_m(old, kb == 0 ? a.Gp : a.A, P, ib * kTile, jb * kTile, kb == 0 && ib == jb, tau,
+                            a.lam_m2, p);
+            else
+                load_tile_m(old, jb == kb ? nullptr : a.Linv, P, ib * kTile, jb * kTile, false, 0.0, nullptr, p);
             load_tiles(S, a.A, k0, ib * kTile, T, part == 0 ? a.A : a.Linv, k0, jb * kTile, P);
             __syncthreads();
-#if HSP_TILE_MFMA
+            stamp(g);
             MAcc acc;
-            gemm_tn_mfma(S, T, acc);
-            if (part == 0)
-                store_tile_m(a.A, P, ib * kTile, jb * kTile, acc, -1.0, kb == 0 ? a.Gp : a.A,
-                             kb == 0 && ib == jb, tau, a.lam_m2, p);
-            else
-                store_tile_m(a.Linv, P, ib * kTile, jb * kTile, acc, -1.0, jb == kb ? nullptr : a.Linv,
-                             false, 0.0, nullptr, p);
-#else
-            double acc[4][4];
-            zero_acc(acc);
             gemm_tn(S, T, acc);
-            if (part == 0)
-                store_tile(a.A, P, ib * kTile, jb * kTile, acc, -1.0, kb == 0 ? a.Gp : a.A,
-                           kb == 0 && ib == jb, tau, a.lam_m2, p);
-            else
-                store_tile(a.Linv, P, ib * kTile, jb * kTile, acc, -1.0, jb == kb ? nullptr : a.Linv,
-                           false, 0.0, nullptr, p);
-#endif
+            put_tile_m(part == 0 ? a.A : a.Linv, P, ib * kTile, jb * kTile, acc, -1.0, old);
             out = part == 0 ? &vU[ib * nt + jb] : &vL[ib * nt + jb];
             val = part == 0 ? kb + 1 : kb - jb + 1;
         }
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) __hip_atomic_store(out, val, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0 && queue) *next_lds = (double)reserved;
+        publish(out, val, out2, 1u);
         stamp(g);
+        n = queue ? n0 + (uint32_t)*next_lds : n + 1;
+        __syncthreads();
     }
     return true;
 }
@@ -974,6 +952,9 @@ __device__ void tile_path(const SweepArgs& a, Group& g, uint32_t rank, uint32_t 
 
 // The whole p-side role of block `rank` of the group.
 __device__ __forceinline__ void pside_role(const SweepArgs& a, uint32_t rank, uint32_t k, double* lds) {
+    // The group's waves share SIMDs with z-pass waves; their latency-bound
+    // chain gets the higher issue priority.
+    __builtin_amdgcn_s_setprio(3);
     Group g;
     g.trace = a.trace ? a.trace + (size_t)rank * kTraceSlots : nullptr;
     if (g.trace && threadIdx.x == 0) g.trace[0] = wall_clock64();
@@ -1000,6 +981,7 @@ __device__ __forceinline__ void pside_role(const SweepArgs& a, uint32_t rank, ui
         if (a.x.p > (uint32_t)kSmallP && (a.mode & kModeBeta)) {
             const uint32_t nt = padded(a.x.p) / kTile;
             for (uint32_t e = threadIdx.x; e < 2 * nt * nt; e += kThreads) a.ver[e] = 0u;
+            if (threadIdx.x == 0) a.ctrl->task_next = 0u;
         }
         __threadfence();
     }

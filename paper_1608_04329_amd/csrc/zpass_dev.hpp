@@ -45,6 +45,11 @@ struct XTraits<1> {  // bfloat16
     static constexpr int BYTES = 2;
 };
 
+#ifndef HSP_X_NONTEMPORAL
+#define HSP_X_NONTEMPORAL 1
+#endif
+typedef unsigned int U32x4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ uint32_t word_of(const uint4& v, int i) {
     return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
 }
@@ -75,6 +80,7 @@ __device__ __forceinline__ void tn_candidate(float mu, bool gauss, float theta, 
 template <int XT, int KC, int R>
 __device__ __forceinline__ void zpass_role(const SweepArgs& a, uint32_t zrank, uint32_t nz,
                                            uint32_t ksweep, double* red) {
+    if (zrank >= nz) return;  // no z-pass work in this launch
     constexpr int VEC = XTraits<XT>::VEC;
     constexpr int EB = XTraits<XT>::BYTES;
     constexpr int CW = kWave * VEC;  // columns covered by one wave-wide 16-byte load
@@ -111,9 +117,15 @@ __device__ __forceinline__ void zpass_role(const SweepArgs& a, uint32_t zrank, u
             for (int kc = 0; kc < KC; ++kc) {
                 const uint32_t row = row0 + r;
                 const uint32_t col = kc * CW + lane * VEC;
-                if (row < N && col < ld)
+                if (row < N && col < ld) {
+#if HSP_X_NONTEMPORAL
+                    const U32x4 v = __builtin_nontemporal_load(
+                        reinterpret_cast<const U32x4*>(Xb + row * row_bytes + (size_t)col * EB));
+                    xr[r][kc] = make_uint4(v.x, v.y, v.z, v.w);
+#else
                     xr[r][kc] = *reinterpret_cast<const uint4*>(Xb + row * row_bytes + (size_t)col * EB);
-                else
+#endif
+                } else
                     xr[r][kc] = make_uint4(0u, 0u, 0u, 0u);
             }
 

@@ -195,15 +195,18 @@ def hsp_philox(seed, ctr):
 
 
 def hsp_tile_schedule(nt, gp):
-    """Per-block task lists of the tiled factorisation: (tasks, offsets)."""
+    """Task lists of the tiled factorisation: (tasks, list bounds).
+
+    One list for a group of one block; otherwise block 0's chain list and the
+    shared queue of the other blocks."""
     n = C.c_int64()
     st = load().hsp_tile_schedule(nt, gp, None, 0, None, C.byref(n))
     if st not in (HSP_OK, HSP_ERANGE):
         _check(st)
     tasks = np.zeros(max(n.value, 1), np.uint32)
-    off = np.zeros(gp + 1, np.uint32)
+    off = np.zeros(3, np.uint32)
     _check(load().hsp_tile_schedule(nt, gp, _hp(tasks), tasks.size, _hp(off), C.byref(n)))
-    return tasks[: n.value], off
+    return tasks[: n.value], off[: 2 if gp == 1 else 3]
 
 
 def hsp_set_phase_trace(h, enable):

@@ -16,22 +16,28 @@ import pytest
 
 from paper_1608_04329_amd import hsp
 
-POTRF, TRSM, GEMM = 0, 1, 2
+POTRF, TRSM, GEMM, PANEL = 0, 1, 2, 3
 
 
 def decode(c):
     return c & 3, (c >> 2) & 1, (c >> 3) & 127, (c >> 10) & 127, (c >> 17) & 127
 
 
-def expected_tasks(nt):
-    """Right-looking blocked Cholesky of [Q | I]: every tile operation once."""
+def expected_tasks(nt, chain):
+    """Right-looking blocked Cholesky of [Q | I]: every tile operation once.
+
+    With a chain block, PANEL(k) (k >= 1) stands for the solve of tile
+    (k-1, k), the update of tile (k, k) at step k-1 and the factorisation of
+    tile (k, k).
+    """
     out = set()
     for k in range(nt):
-        out.add((POTRF, 0, k, k, k))
-        out.update((TRSM, 0, k, k, j) for j in range(k + 1, nt))
+        out.add((PANEL, 0, k, k, k) if chain and k > 0 else (POTRF, 0, k, k, k))
+        out.update((TRSM, 0, k, k, j) for j in range(k + 1, nt) if not (chain and j == k + 1))
         out.update((TRSM, 1, k, k, j) for j in range(k))
         for i in range(k + 1, nt):
-            out.update((GEMM, 0, k, i, j) for j in range(i, nt))
+            out.update((GEMM, 0, k, i, j) for j in range(i, nt)
+                       if not (chain and i == j == k + 1))
             out.update((GEMM, 1, k, i, j) for j in range(k + 1))
     return out
 
@@ -40,6 +46,8 @@ def reads_ok(t, vU, vL):
     typ, part, k, i, j = t
     if typ == POTRF:
         return vU[k, k] >= k
+    if typ == PANEL:
+        return vU[k - 1, k] >= k - 1 and vU[k, k] >= k - 1
     if typ == TRSM:
         return vU[k, k] >= k + 1 and (vU[k, j] >= k if part == 0 else vL[k, j] >= k - j)
     if part == 0:
@@ -49,7 +57,12 @@ def reads_ok(t, vU, vL):
 
 def write(t, vU, vL):
     typ, part, k, i, j = t
-    if typ == POTRF:
+    if typ == PANEL:
+        assert vU[k - 1, k] == k - 1 and vU[k, k] == k - 1
+        vU[k - 1, k] = k
+        vU[k, k] = k + 1
+        vL[k, k] = 1
+    elif typ == POTRF:
         assert vU[k, k] == k
         vU[k, k] = k + 1
         vL[k, k] = 1
@@ -63,25 +76,45 @@ def write(t, vU, vL):
         vL[r, c] = k - j + 1
 
 
-def replay(lists, nt, rng):
-    """Event simulation: each block runs its list in order, waiting on versions."""
+def replay(chain_list, queue, nqb, nt, rng):
+    """Event simulation of the device: block 0 runs chain_list in order; nqb
+    other blocks claim queue entries in order, each reserving its next entry
+    when it starts a task (as the kernel does), and wait on tile versions."""
     vU = np.zeros((nt, nt), np.int64)
     vL = np.zeros((nt, nt), np.int64)
-    pos = [0] * len(lists)
+    nb = 1 + nqb
+    claimed = 0
+
+    def claim():
+        nonlocal claimed
+        claimed += 1
+        return claimed - 1
+
+    cur = [0] + [claim() for _ in range(nqb)]  # block 0: index into chain_list
+    nxt = [None] * nb
     running = []  # heap of (finish time, block)
-    busy = [False] * len(lists)
+    busy = [False] * nb
     now = 0.0
-    left = sum(len(l) for l in lists)
+    left = len(chain_list) + len(queue)
+
+    def task_of(b):
+        if b == 0:
+            return chain_list[cur[0]] if cur[0] < len(chain_list) else None
+        return queue[cur[b]] if cur[b] < len(queue) else None
+
     while left:
-        for b, l in enumerate(lists):
-            if not busy[b] and pos[b] < len(l) and reads_ok(l[pos[b]], vU, vL):
-                dur = rng.uniform(0.3, 3.0) * (6.0 if l[pos[b]][0] == POTRF else 1.0)
+        for b in range(nb):
+            t = task_of(b)
+            if not busy[b] and t is not None and reads_ok(t, vU, vL):
+                if b > 0:
+                    nxt[b] = claim()
+                dur = rng.uniform(0.3, 3.0) * (4.0 if t[0] in (POTRF, PANEL) else 1.0)
                 heapq.heappush(running, (now + dur, b))
                 busy[b] = True
         assert running, f"deadlock with {left} tasks left"
         now, b = heapq.heappop(running)
-        write(lists[b][pos[b]], vU, vL)
-        pos[b] += 1
+        write(task_of(b), vU, vL)
+        cur[b] = cur[b] + 1 if b == 0 else nxt[b]
         busy[b] = False
         left -= 1
     for i in range(nt):
@@ -93,27 +126,39 @@ def replay(lists, nt, rng):
     return now
 
 
+def lists_of(nt, gp):
+    tasks, off = hsp.hsp_tile_schedule(nt, gp)
+    dec = [decode(int(c)) for c in tasks]
+    if gp == 1:
+        assert len(off) == 2
+        return dec, [], 0  # one block: its list as the "chain"
+    assert len(off) == 3
+    return dec[off[0]:off[1]], dec[off[1]:off[2]], gp - 1
+
+
 @pytest.mark.parametrize("nt,gp", [(1, 1), (2, 1), (3, 2), (5, 32), (16, 32), (16, 7), (20, 32)])
 def test_schedule_covers_every_task_and_never_deadlocks(nt, gp):
     tasks, off = hsp.hsp_tile_schedule(nt, gp)
     assert off[0] == 0 and off[-1] == len(tasks) and np.all(np.diff(off.astype(np.int64)) >= 0)
-    dec = [decode(int(c)) for c in tasks]
-    assert len(dec) == len(set(dec)) and set(dec) == expected_tasks(nt)
-    lists = [dec[off[b]:off[b + 1]] for b in range(gp)]
+    chain_list, queue, nqb = lists_of(nt, gp)
+    dec = chain_list + queue
+    chain = gp > 1
+    assert len(dec) == len(set(dec)) and set(dec) == expected_tasks(nt, chain)
+    if chain:  # block 0 runs the critical chain, in order, and nothing else
+        assert chain_list == [(POTRF, 0, 0, 0, 0)] + [(PANEL, 0, k, k, k) for k in range(1, nt)]
     rng = np.random.default_rng(nt * 100 + gp)
     for _ in range(5 if nt < 16 else 2):
-        replay(lists, nt, rng)
+        replay(chain_list, queue, nqb, nt, rng)
 
 
 def test_schedule_shortens_with_more_blocks():
     """The critical path is fixed; more blocks only help until it dominates."""
     spans = {}
-    for gp in (1, 4, 32):
-        tasks, off = hsp.hsp_tile_schedule(16, gp)
-        dec = [decode(int(c)) for c in tasks]
-        lists = [dec[off[b]:off[b + 1]] for b in range(gp)]
-        spans[gp] = np.mean([replay(lists, 16, np.random.default_rng(s)) for s in range(2)])
-    assert spans[32] < spans[4] < spans[1]
+    for gp in (2, 4, 32):
+        chain_list, queue, nqb = lists_of(16, gp)
+        spans[gp] = np.mean([replay(chain_list, queue, nqb, 16, np.random.default_rng(s))
+                             for s in range(2)])
+    assert spans[32] < spans[4] < spans[2]
 
 
 def test_schedule_rejects_bad_arguments():
