@@ -59,10 +59,11 @@ __device__ __forceinline__ bool group_failed(const Group& g, double* lds_flag) {
 }
 
 // Thread 0 only: wait until *ctr >= target, or give up after the timeout.
+// Relaxed polls; the caller orders its later reads with one acquire fence.
 __device__ __forceinline__ void wait_count(unsigned long long* ctr, unsigned long long target,
                                         Ctrl* ctrl, uint64_t timeout) {
     const uint64_t t0 = wall_clock64();
-    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         if (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout)
             break;
         if (wall_clock64() - t0 > timeout) {
@@ -72,6 +73,12 @@ __device__ __forceinline__ void wait_count(unsigned long long* ctr, unsigned lon
         __builtin_amdgcn_s_sleep(2);
     }
 }
+
+// Cross-block ordering, one fence per block: before publishing, every wave
+// waits for its own stores and one thread writes the cache back (release);
+// after observing, one thread invalidates (acquire) before the block reads.
+__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 // Thread 0: next trace timestamp, or a given value (diagnostics only).
 __device__ __forceinline__ void stamp(Group& g) {
@@ -86,12 +93,22 @@ __device__ __forceinline__ void stamp_at(uint64_t* rec, int s) {
     if (rec && threadIdx.x == 0) rec[s] = wall_clock64();
 }
 
-// Thread 0 only: wait until *ver >= need; false if the group is failing or
-// the wait timed out.
-__device__ __forceinline__ bool wait_ver(uint32_t* ver, uint32_t need, Ctrl* ctrl, uint64_t timeout) {
-    if (__hip_atomic_load(ver, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= need) return true;
-    const uint64_t t0 = wall_clock64();
-    while (__hip_atomic_load(ver, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+// Thread 0 only: wait until *v[i] >= need[i] for i < n (the n loads of a poll
+// are in flight together); false if the group is failing or the wait timed
+// out.  Relaxed polls: the caller follows a success with fence_acquire().
+__device__ __forceinline__ bool wait_vers(uint32_t* const (&v)[3], const uint32_t (&need)[3], int n,
+                                          Ctrl* ctrl, uint64_t timeout) {
+    uint64_t t0 = 0;
+    for (int it = 0;; ++it) {
+        uint32_t got[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            got[i] = i < n ? __hip_atomic_load(v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        bool ok = true;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) ok = ok && (i >= n || got[i] >= need[i]);
+        if (ok) return true;
+        if (it == 0) t0 = wall_clock64();
         if (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
             (kErrTimeout | kErrNotPD))
             return false;
@@ -101,34 +118,32 @@ __device__ __forceinline__ bool wait_ver(uint32_t* ver, uint32_t need, Ctrl* ctr
         }
         __builtin_amdgcn_s_sleep(1);
     }
-    return true;
 }
 
 // Make this block's global stores visible device-wide, then set *ver = val
-// (and *ver2 = val2):
-// every wave waits for its own stores, and one thread writes the cache back
-// and publishes (a release fence per block, not per wave).
+// (and *ver2 = val2): every wave waits for its own stores, one thread writes
+// the cache back and publishes.
 __device__ __forceinline__ void publish(uint32_t* ver, uint32_t val, uint32_t* ver2 = nullptr,
                                         uint32_t val2 = 0) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        __hip_atomic_store(ver, val, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        if (ver2) __hip_atomic_store(ver2, val2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        fence_release();
+        __hip_atomic_store(ver, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ver2) __hip_atomic_store(ver2, val2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 __device__ __forceinline__ void group_sync(Group& g) {
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0 && g.size > 1) {
+    if (threadIdx.x == 0) {
+        fence_release();
         atomicAdd(&g.ctrl->bar_count, 1ull);
-        wait_count(&g.ctrl->bar_count, g.base + (unsigned long long)(g.n + 1) * g.size, g.ctrl,
-                   g.timeout);
-        __threadfence();
-    } else if (threadIdx.x == 0) {
-        atomicAdd(&g.ctrl->bar_count, 1ull);
+        if (g.size > 1)
+            wait_count(&g.ctrl->bar_count, g.base + (unsigned long long)(g.n + 1) * g.size, g.ctrl,
+                       g.timeout);
+        fence_acquire();
     }
     g.n++;
     stamp(g);
@@ -356,9 +371,11 @@ __device__ void small_path(const SweepArgs& a, Group& g, uint32_t k, double* lds
         }
     }
     if (a.mode & kModeZ) {
-        if (threadIdx.x == 0) wait_count(&a.ctrl->z_count, g.zbase + a.zgroups, a.ctrl, a.timeout_ticks);
+        if (threadIdx.x == 0) {
+            wait_count(&a.ctrl->z_count, g.zbase + a.zgroups, a.ctrl, a.timeout_ticks);
+            fence_acquire();
+        }
         __syncthreads();
-        __threadfence();
         // one column per thread, summed over the group partial rows in order
         for (uint32_t j = threadIdx.x; j < p; j += kThreads) {
             double s = 0.0;
@@ -726,25 +743,35 @@ __device__ bool run_tasks(const SweepArgs& a, Group& g, uint32_t rank, double ta
         uint32_t reserved = 0;
         if (threadIdx.x == 0) {
             if (queue) reserved = atomicAdd(&a.ctrl->task_next, 1u);
-            bool w = true;
+            uint32_t* v[3] = {nullptr, nullptr, nullptr};
+            uint32_t need[3] = {0u, 0u, 0u};
+            int nv;
             if (type == kTaskPotrf) {
-                w = wait_ver(&vU[kb * nt + kb], kb, a.ctrl, g.timeout);
+                v[0] = &vU[kb * nt + kb], need[0] = kb;
+                nv = 1;
             } else if (type == kTaskPanel) {
-                w = wait_ver(&vU[(kb - 1) * nt + kb], kb - 1, a.ctrl, g.timeout) &&
-                    wait_ver(&vU[kb * nt + kb], kb - 1, a.ctrl, g.timeout);
+                v[0] = &vU[(kb - 1) * nt + kb], need[0] = kb - 1;
+                v[1] = &vU[kb * nt + kb], need[1] = kb - 1;
+                nv = 2;
             } else if (type == kTaskTrsm) {
-                w = wait_ver(&vU[kb * nt + kb], kb + 1, a.ctrl, g.timeout) &&
-                    (part == 0 ? wait_ver(&vU[kb * nt + jb], kb, a.ctrl, g.timeout)
-                               : wait_ver(&vL[kb * nt + jb], kb - jb, a.ctrl, g.timeout));
+                v[0] = &vU[kb * nt + kb], need[0] = kb + 1;
+                if (part == 0) v[1] = &vU[kb * nt + jb], need[1] = kb;
+                else v[1] = &vL[kb * nt + jb], need[1] = kb - jb;
+                nv = 2;
             } else {
-                w = wait_ver(&vU[kb * nt + ib], kb + 1, a.ctrl, g.timeout) &&
-                    (part == 0 ? wait_ver(&vU[kb * nt + jb], kb + 1, a.ctrl, g.timeout) &&
-                                     wait_ver(&vU[ib * nt + jb], kb, a.ctrl, g.timeout)
-                               : wait_ver(&vL[kb * nt + jb], kb - jb + 1, a.ctrl, g.timeout) &&
-                                     wait_ver(&vL[ib * nt + jb], kb - jb, a.ctrl, g.timeout));
+                v[0] = &vU[kb * nt + ib], need[0] = kb + 1;
+                if (part == 0) {
+                    v[1] = &vU[kb * nt + jb], need[1] = kb + 1;
+                    v[2] = &vU[ib * nt + jb], need[2] = kb;
+                } else {
+                    v[1] = &vL[kb * nt + jb], need[1] = kb - jb + 1;
+                    v[2] = &vL[ib * nt + jb], need[2] = kb - jb;
+                }
+                nv = 3;
             }
+            const bool w = wait_vers(v, need, nv, a.ctrl, g.timeout);
             *flag = w ? 0.0 : 1.0;
-            __threadfence();
+            fence_acquire();
         }
         __syncthreads();
         stamp_value(g, n + 1u);
@@ -874,10 +901,12 @@ __device__ void tile_path(const SweepArgs& a, Group& g, uint32_t rank, uint32_t 
     }
 
     if (a.mode & kModeZ) {
-        if (threadIdx.x == 0) wait_count(&a.ctrl->z_count, g.zbase + a.zgroups, a.ctrl, a.timeout_ticks);
+        if (threadIdx.x == 0) {
+            wait_count(&a.ctrl->z_count, g.zbase + a.zgroups, a.ctrl, a.timeout_ticks);
+            fence_acquire();
+        }
         if (g.trace && threadIdx.x == 0) g.trace[kTraceSlots - 1] = wall_clock64();
         __syncthreads();
-        __threadfence();
         const uint32_t per = ((p + g.size - 1) / g.size + 15) / 16 * 16;
         const uint32_t c0 = rank * per, c1 = min(p, c0 + per);
         if (c0 < c1) reduce_b_cols(a, c0, c1, lds);

@@ -238,21 +238,25 @@ __device__ __forceinline__ void zpass_role(const SweepArgs& a, uint32_t zrank, u
     // This block's partial is complete.  The last of each group of kZGroup
     // consecutive blocks to finish adds the group's partials in block order
     // (deterministic) and publishes the group sum; the p-side waits for all
-    // groups.  Every thread's stores are made visible device-wide first.
-    __threadfence();
+    // groups.  Every wave waits for its own stores; one thread writes the
+    // cache back before arriving, and the last arriver invalidates before
+    // reading the others' partials.
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     const uint32_t grp = zrank / kZGroup;
     const uint32_t g0 = grp * kZGroup;
     const uint32_t gsize = min((uint32_t)kZGroup, nz - g0);
     if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const uint32_t old = atomicAdd(&a.zgrp_count[grp], 1u);
-        red[0] = (old == gsize - 1) ? 1.0 : 0.0;
+        const bool lst = old == gsize - 1;
+        if (lst) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        red[0] = lst ? 1.0 : 0.0;
     }
     __syncthreads();
     const bool last = red[0] != 0.0;
     __syncthreads();
     if (last) {
-        __threadfence();
         for (uint32_t c = threadIdx.x; c < ld; c += kThreads) {
             double v[kZGroup];
 #pragma unroll
@@ -263,11 +267,11 @@ __device__ __forceinline__ void zpass_role(const SweepArgs& a, uint32_t zrank, u
             for (int r = 1; r < kZGroup; ++r) s += v[r];
             a.gpartial[(size_t)grp * ld + c] = s;
         }
-        __threadfence();
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0) {
             a.zgrp_count[grp] = 0u;  // every block of the group has arrived
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             atomicAdd(&a.ctrl->z_count, 1ull);
         }
     }
