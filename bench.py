@@ -7,9 +7,12 @@ Inputs are seeded synthetic data (the paper's Section 6.1 design with an
 intercept and 10 nonzero coefficients) resident in HBM before timing starts.
 
 Prints one JSON line.  Also reports:
-  roofline      the z pass (the dominant kernel): algorithmic bytes per launch
-                (N p 4 + N) over its mean duration from HIP events on the
-                library's stream, against the 8 TB/s HBM peak
+  roofline      the sweep kernel (one fused launch per sweep; its z pass is the
+                N x p stream): algorithmic bytes per launch (N p 4 + N) over
+                its mean duration from HIP events on the library's stream,
+                against the 8 TB/s HBM peak; traffic = hardware-counted HBM
+                bytes per launch when the stored counter reading matches the
+                current kernel sources
   cpu_baseline  the float64 oracle timed on this host on a bounded sample of
                 the same workload (whole sweeps, one thread)
 """
@@ -36,8 +39,23 @@ def parse():
     ap.add_argument("--x-type", default="f32", choices=["f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "zpass_traffic.json"))
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "sweep_kernel_traffic.json"))
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device to device twice (a plain copy kernel of known "
+                         "size, to scale hardware byte counters)")
     return ap.parse_args()
+
+
+def kernel_fingerprint():
+    """Hash of the HIP sources: stored counter readings apply only to the same kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1608_04329_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(d, seconds):
@@ -78,6 +96,16 @@ def main():
     from paper_1608_04329_amd import hsp
 
     torch.cuda.set_device(0)
+    if a.copy_calibration:
+        n = a.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: 2 copies of {a.copy_calibration} MiB", file=sys.stderr,
+              flush=True)
+        del src, dst
     t0 = time.perf_counter()
     beta_true, idx = synth.sparse_beta(a.p, min(10, a.p - 1), 13)
     d = synth.probit_design(a.N, a.p, beta_true, 13, True, f"n{a.N}_p{a.p}")
@@ -101,8 +129,8 @@ def main():
     zpass_ms, sweep_ms, n_timed = s.timing()
     clamps, maxatt = s.counters()
     s.set_timing(False)
-    print(f"[bench] {a.steps} sweeps in {elapsed:.3f}s; z pass {zpass_ms:.4f} ms, "
-          f"sweep {sweep_ms:.4f} ms (events)", file=sys.stderr, flush=True)
+    print(f"[bench] {a.steps} sweeps in {elapsed:.3f}s; sweep kernel {zpass_ms:.4f} ms per launch, "
+          f"{sweep_ms:.4f} ms per sweep (events)", file=sys.stderr, flush=True)
 
     esz = 4 if a.x_type == "f32" else 2
     zbytes = a.N * a.p * esz + a.N  # X once, y once
@@ -112,9 +140,10 @@ def main():
     if os.path.exists(a.traffic_json):
         try:
             t = json.load(open(a.traffic_json))
-            if t.get("workload") == d.name and t.get("x_type") == a.x_type:
+            if (t.get("workload") == d.name and t.get("x_type") == a.x_type
+                    and t.get("kernel_fingerprint") == kernel_fingerprint()):
                 traffic = t.get("bytes_per_launch")
-        except Exception:
+        except (OSError, ValueError):
             traffic = None
     out = {
         "metric": METRIC,
@@ -133,8 +162,9 @@ def main():
                    "N": a.N, "p": a.p, "x_storage": a.x_type, "n_side_arith": "f32",
                    "p_side_arith": "f64", "chains": 1},
         "hbm_gbps": round(zbytes / (elapsed / a.steps) / 1e9, 1),
-        "zpass_ms": round(zpass_ms, 5),
+        "kernel_ms": round(zpass_ms, 5),
         "sweep_ms_events": round(sweep_ms, 5),
+        "kernel_fingerprint": kernel_fingerprint(),
         "max_tn_proposals": int(maxatt),
         "lambda_clamps": int(clamps),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
@@ -143,6 +173,7 @@ def main():
     }
     s.close()
     if not a.no_cpu_baseline:
+        print("[bench] timing the float64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(d, a.cpu_seconds)
     print(json.dumps(out), flush=True)
 
