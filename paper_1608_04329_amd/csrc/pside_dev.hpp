@@ -265,26 +265,6 @@ __device__ void hyper_nu_xi(const SweepArgs& a, uint32_t k) {
     }
 }
 
-// b = sum of the z-pass groups' partial rows, columns [c0, c1) by this block,
-// 16 columns x 16 row groups at a time, in a fixed order.
-__device__ void reduce_b_cols(const SweepArgs& a, uint32_t c0, uint32_t c1, double* red) {
-    const int tc = threadIdx.x & 15, tr = threadIdx.x >> 4;
-    for (uint32_t cb = c0; cb < c1; cb += 16) {
-        const uint32_t col = cb + tc;
-        double s = 0.0;
-        if (col < c1)
-            for (uint32_t r = tr; r < a.zgroups; r += 16) s += a.gpartial[(size_t)r * a.x.ld + col];
-        red[tr * 17 + tc] = s;
-        __syncthreads();
-        if (tr == 0 && col < c1) {
-            double t = 0.0;
-            for (int i = 0; i < 16; ++i) t += red[i * 17 + tc];
-            a.b[col] = t;
-        }
-        __syncthreads();
-    }
-}
-
 // ---- one-block path, p <= 128 ----------------------------------------------------
 __device__ __forceinline__ uint32_t pk(uint32_t p, uint32_t i, uint32_t j) {
     // packed upper triangle, row-major: row i starts at i p - i (i - 1) / 2
@@ -907,30 +887,64 @@ __device__ void tile_path(const SweepArgs& a, Group& g, uint32_t rank, uint32_t 
         }
         if (g.trace && threadIdx.x == 0) g.trace[kTraceSlots - 1] = wall_clock64();
         __syncthreads();
-        const uint32_t per = ((p + g.size - 1) / g.size + 15) / 16 * 16;
-        const uint32_t c0 = rank * per, c1 = min(p, c0 + per);
-        if (c0 < c1) reduce_b_cols(a, c0, c1, lds);
-        group_sync(g);
     }
+    // b = X^T z into LDS (zero on the padding): every block sums the z groups'
+    // partials itself, rows in ascending order, so all hold the same b and no
+    // barrier is needed; block 0 also stores it.  Eight rows of loads are in
+    // flight per column.
+    double* bl = lds;
+    for (uint32_t j = threadIdx.x; j < P; j += kThreads) {
+        double s = 0.0;
+        if (j < p) {
+            if (a.mode & kModeZ) {
+                const double* gcol = a.gpartial + j;
+                for (uint32_t r0 = 0; r0 < a.zgroups; r0 += 8) {
+                    double v[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        v[q] = r0 + q < a.zgroups ? gcol[(size_t)(r0 + q) * a.x.ld] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) s += v[q];
+                }
+                if (rank == 0) a.b[j] = s;
+            } else {
+                s = a.b[j];
+            }
+        }
+        bl[j] = s;
+    }
+    __syncthreads();
 
     if ((a.mode & kModeBeta) && ok) {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        // y = L^-1 b + s: four rows per wave at a time, b from LDS
-        double* bl = lds;
-        for (uint32_t j = threadIdx.x; j < p; j += kThreads) bl[j] = a.b[j];
-        __syncthreads();
+        // y = L^-1 b + s, four rows per wave at a time.  L^-1 is zero above the
+        // diagonal and the identity on the padding, and b is zero there, so
+        // the sums need no bounds: row i runs over every column up to the
+        // group's last row.  Rows are dealt so that each wave gets short and
+        // long ones.
         double* yv = a.vec;
         for (uint32_t i0 = (rank * 4 + wave) * 4; i0 < p; i0 += g.size * 16) {
             double acc[4] = {0.0, 0.0, 0.0, 0.0};
-            const uint32_t iend = min(i0 + 3, p - 1);  // row i sums j <= i
-#pragma unroll 4
-            for (uint32_t j = lane; j <= iend; j += 64) {
+            const double* L0 = a.Linv + (size_t)i0 * P;
+            const uint32_t jn = i0 + 4;
+            uint32_t j = lane;
+            for (; j + 192 < jn; j += 256) {
+                double x[4][4], bj[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    bj[u] = bl[j + 64 * u];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) x[u][r] = L0[(size_t)r * P + j + 64 * u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[r] = fma(x[u][r], bj[u], acc[r]);
+            }
+            for (; j < jn; j += 64) {
                 const double bj = bl[j];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const uint32_t i = i0 + r;
-                    if (i < p && j <= i) acc[r] = fma(a.Linv[(size_t)i * P + j], bj, acc[r]);
-                }
+                for (int r = 0; r < 4; ++r) acc[r] = fma(L0[(size_t)r * P + j], bj, acc[r]);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -944,35 +958,46 @@ __device__ void tile_path(const SweepArgs& a, Group& g, uint32_t rank, uint32_t 
             }
         }
         group_sync(g);
-        // beta = L^-T y: 32 columns x 8 row groups per pass, y from LDS
+        // beta = L^-T y, y from LDS (zero on the padding); column j sums rows
+        // i >= j, the rest of L^-1 being zero.  Block r takes two 16-column
+        // blocks, one from each end (columns 16 r and P - 16 (r + 1) on), so
+        // every block reads about the same number of rows; 16 row groups per
+        // column, four rows of loads in flight each.
         double* yl = lds;
-        for (uint32_t j = threadIdx.x; j < p; j += kThreads) yl[j] = yv[j];
+        for (uint32_t j = threadIdx.x; j < P; j += kThreads) yl[j] = j < p ? yv[j] : 0.0;
         double* red = lds + P;
         __syncthreads();
         bool keep;
         const uint32_t slot = record_slot(a, k, &keep);
-        const int tc = threadIdx.x & 31, tr = threadIdx.x >> 5;
+        const int tc = threadIdx.x & 15, tr = threadIdx.x >> 4;
         bool nonfinite = false;
-        for (uint32_t cb = rank * 32; cb < p; cb += g.size * 32) {
-            const uint32_t col = cb + tc;
-            double acc = 0.0;
-#pragma unroll 4
-            for (uint32_t i = cb + tr; i < p; i += 8)
-                if (i >= col) acc = fma(a.Linv[(size_t)i * P + col], yl[i], acc);
-            red[tr * 33 + tc] = acc;
-            __syncthreads();
-            if (tr == 0 && col < p) {
-                double bi = 0.0;
-                for (int q = 0; q < 8; ++q) bi += red[q * 33 + tc];
-                a.beta[col] = bi;
-                a.beta32[col] = (float)bi;
-                if (!isfinite(bi)) nonfinite = true;
-                if (keep) {
-                    a.ring_beta[(size_t)slot * p + col] = bi;
-                    if (a.ring_lam) a.ring_lam[(size_t)slot * p + col] = a.lam_m2[col];
+        for (uint32_t cb0 = rank * 16; cb0 < P / 2; cb0 += g.size * 16) {
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const uint32_t cb = half == 0 ? cb0 : P - 16 - cb0;
+                const uint32_t col = cb + tc;
+                const double* Lc = a.Linv + col;
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                uint32_t i = cb + tr;
+                for (; i + 48 < P; i += 64)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[u] = fma(Lc[(size_t)(i + 16 * u) * P], yl[i + 16 * u], acc[u]);
+                for (; i < P; i += 16) acc[0] = fma(Lc[(size_t)i * P], yl[i], acc[0]);
+                red[tr * 17 + tc] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+                __syncthreads();
+                if (tr == 0 && col < p) {
+                    double bi = 0.0;
+                    for (int q = 0; q < 16; ++q) bi += red[q * 17 + tc];
+                    a.beta[col] = bi;
+                    a.beta32[col] = (float)bi;
+                    if (!isfinite(bi)) nonfinite = true;
+                    if (keep) {
+                        a.ring_beta[(size_t)slot * p + col] = bi;
+                        if (a.ring_lam) a.ring_lam[(size_t)slot * p + col] = a.lam_m2[col];
+                    }
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
         if (nonfinite) atomicOr(&a.ctrl->err, kErrNonFinite);
         if (keep && rank == 0 && threadIdx.x == 0) a.ring_tau[slot] = current_tau(a);
