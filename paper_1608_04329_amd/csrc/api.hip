@@ -85,39 +85,39 @@ hipError_t dalloc(T** p, size_t n) {
 SweepArgs sweep_args(hsp_state* s, uint32_t mode) {
     SweepArgs a{};
     a.x = s->x;
-    a.y = s->y;
-    a.beta32 = s->beta32;
-    a.partial = s->partial;
-    a.gpartial = s->gpartial;
-    a.zgrp_count = s->zgrp_count;
-    a.zdbg = s->opt.debug_store_z ? s->zdbg : nullptr;
-    a.adbg = s->opt.debug_store_z ? s->adbg : nullptr;
-    a.beta = s->beta;
-    a.lam_m2 = s->lam;
-    a.nu_m1 = s->nu;
-    a.tau_m2 = s->tau;
-    a.xi_m1 = s->xi;
-    a.b = s->b;
-    a.G = s->G;
-    a.Gp = s->Gp;
-    a.A = s->A;
-    a.Linv = s->Linv;
-    a.Dinv = s->Dinv;
-    a.tasks = s->tasks;
-    a.task_off = s->task_off;
-    a.ver = s->ver;
-    a.vec = s->vec;
-    a.ring_beta = s->ring_beta;
-    a.ring_tau = s->ring_tau;
-    a.ring_lam = s->ring_lam;
+    a.y = dev_ptr(s->y);
+    a.beta32 = dev_ptr(s->beta32);
+    a.partial = dev_ptr(s->partial);
+    a.gpartial = dev_ptr(s->gpartial);
+    a.zgrp_count = dev_ptr(s->zgrp_count);
+    a.zdbg = dev_ptr(s->opt.debug_store_z ? s->zdbg : nullptr);
+    a.adbg = dev_ptr(s->opt.debug_store_z ? s->adbg : nullptr);
+    a.beta = dev_ptr(s->beta);
+    a.lam_m2 = dev_ptr(s->lam);
+    a.nu_m1 = dev_ptr(s->nu);
+    a.tau_m2 = dev_ptr(s->tau);
+    a.xi_m1 = dev_ptr(s->xi);
+    a.b = dev_ptr(s->b);
+    a.G = dev_ptr(s->G);
+    a.Gp = dev_ptr(s->Gp);
+    a.A = dev_ptr(s->A);
+    a.Linv = dev_ptr(s->Linv);
+    a.Dinv = dev_ptr(s->Dinv);
+    a.tasks = dev_ptr(s->tasks);
+    a.task_off = dev_ptr(s->task_off);
+    a.ver = dev_ptr(s->ver);
+    a.vec = dev_ptr(s->vec);
+    a.ring_beta = dev_ptr(s->ring_beta);
+    a.ring_tau = dev_ptr(s->ring_tau);
+    a.ring_lam = dev_ptr(s->ring_lam);
     a.thin = (uint32_t)s->opt.thin;
     a.capacity = (uint32_t)s->opt.max_draws;
-    a.ctrl = s->ctrl;
+    a.ctrl = dev_ptr(s->ctrl);
     a.seed = s->opt.seed;
     a.chain = s->opt.chain_id;
     a.mode = mode;
     a.timeout_ticks = s->timeout_ticks;
-    a.trace = s->trace;
+    a.trace = dev_ptr(s->trace);
     a.gp = a.gz = a.zgroups = 0;
     return a;
 }
@@ -240,7 +240,7 @@ hsp_status create_impl(hsp_state* s, const float* X, const uint8_t* y, int64_t N
     const uint32_t ld = (uint32_t)((p + align - 1) / align * align);
     const size_t esz = xt == HSP_X_F32 ? 4 : 2;
     HIP_TRY(hipMalloc(&s->Xbuf, (size_t)N * ld * esz));
-    s->x.X = s->Xbuf;
+    s->x.X = dev_ptr(static_cast<const void*>(s->Xbuf));
     s->x.xtype = xt;
     s->x.N = (uint32_t)N;
     s->x.p = (uint32_t)p;

@@ -7,6 +7,22 @@
 
 namespace hsp {
 
+// Pointers that device code reads from memory (the launch description) lose
+// their address space: qualifying them as global in the device pass keeps
+// every access a global (not flat) memory instruction.  The layout is the
+// same in both passes (64-bit pointers).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define HSP_GLOBAL __attribute__((address_space(1)))
+#else
+#define HSP_GLOBAL
+#endif
+
+// Host side: a device pointer as stored in a launch description.
+template <class T>
+inline HSP_GLOBAL T* dev_ptr(T* p) {
+    return (HSP_GLOBAL T*)p;
+}
+
 constexpr int kWave = 64;
 constexpr int kMaxP = 4096;            // largest p the register-tiled z pass supports
 constexpr uint32_t kMaxRounds = 2048;  // 4096 truncated-normal proposals per row
@@ -24,19 +40,20 @@ constexpr int kZGroup = 16;            // z-pass blocks whose partials one block
 constexpr int kTileLd = kTile + 2;
 constexpr int kLdsDoubles = 2 * kTile * kTileLd;
 
-// Device control block, one per sampler state.
+// Device control block, one per sampler state.  The counters that blocks
+// poll or update concurrently each have a 128-byte line of their own.
 struct Ctrl {
     uint32_t sweep;             // completed sweeps; sweep k uses counter k = sweep + 1
     uint32_t draw_base;         // value of sweep at creation or the last set_state
-    uint32_t err;               // kErr* bits
     uint32_t max_attempts;      // most proposals any row needed
-    unsigned long long clamps;  // lambda rates clamped to DBL_MIN
     int32_t chol_info;          // first non-positive pivot (1-based), 0 if none
-    uint32_t task_next;         // next factorisation task of the shared queue (zero between launches)
-    unsigned long long bar_count;  // arrivals at p-side group barriers (monotonic)
+    unsigned long long clamps;  // lambda rates clamped to DBL_MIN
     unsigned long long bar_epoch;  // bar_count when the current launch started
-    unsigned long long z_count;    // z-pass blocks finished (monotonic)
     unsigned long long z_epoch;    // z_count when the current launch started
+    alignas(128) uint32_t err;     // kErr* bits
+    alignas(128) unsigned long long bar_count;  // arrivals at p-side group barriers (monotonic)
+    alignas(128) unsigned long long z_count;    // z-pass groups finished (monotonic)
+    alignas(128) uint32_t task_next;  // next factorisation task of the shared queue (zero between launches)
 };
 
 enum : uint32_t {
@@ -61,7 +78,7 @@ enum : uint32_t {
 // Layout of X in device memory: row-major, leading dimension ld elements,
 // ld a multiple of 16 bytes, padding columns zero.
 struct XLayout {
-    const void* X;
+    HSP_GLOBAL const void* X;
     int xtype;  // 0 float32, 1 bfloat16
     uint32_t N;
     uint32_t p;
@@ -71,31 +88,31 @@ struct XLayout {
 // Everything one launch of the sweep kernel touches.
 struct SweepArgs {
     XLayout x;
-    const uint8_t* y;
-    float* beta32;      // ld floats (padding zero): beta for the z pass
-    double* partial;    // gz x ld: per-block float64 partials of X^T z
-    double* gpartial;   // zgroups x ld: sums of kZGroup consecutive block partials
-    uint32_t* zgrp_count;  // zgroups arrival counters (zero between launches)
-    float* zdbg;        // optional: z of the last z pass (N)
-    int32_t* adbg;      // optional: accepted proposal | gauss bit (N)
-    double* beta;       // p
-    double* lam_m2;     // p
-    double* nu_m1;      // p
-    double* tau_m2;     // 1
-    double* xi_m1;      // 1
-    double* b;          // p: X^T z of the current sweep
-    const double* G;    // p x p Gram
-    const double* Gp;   // tile path: P x P, G with an identity block on the padding
-    double* A;          // tile path, P x P: U (P = p rounded up to 64)
-    double* Linv;       // tile path, P x P: lower triangle holds L^-1 = U^-T
-    double* Dinv;       // ceil(p/64) x 64 x 64: inverses of U's diagonal blocks
-    double* vec;        // 2 p scratch
-    double* ring_beta;  // capacity x p
-    double* ring_tau;   // capacity
-    double* ring_lam;   // capacity x p or null
+    HSP_GLOBAL const uint8_t* y;
+    HSP_GLOBAL float* beta32;      // ld floats (padding zero): beta for the z pass
+    HSP_GLOBAL double* partial;    // gz x ld: per-block float64 partials of X^T z
+    HSP_GLOBAL double* gpartial;   // zgroups x ld: sums of kZGroup consecutive block partials
+    HSP_GLOBAL uint32_t* zgrp_count;  // zgroups arrival counters (zero between launches)
+    HSP_GLOBAL float* zdbg;        // optional: z of the last z pass (N)
+    HSP_GLOBAL int32_t* adbg;      // optional: accepted proposal | gauss bit (N)
+    HSP_GLOBAL double* beta;       // p
+    HSP_GLOBAL double* lam_m2;     // p
+    HSP_GLOBAL double* nu_m1;      // p
+    HSP_GLOBAL double* tau_m2;     // 1
+    HSP_GLOBAL double* xi_m1;      // 1
+    HSP_GLOBAL double* b;          // p: X^T z of the current sweep
+    HSP_GLOBAL const double* G;    // p x p Gram
+    HSP_GLOBAL const double* Gp;   // tile path: P x P, G with an identity block on the padding
+    HSP_GLOBAL double* A;          // tile path, P x P: U (P = p rounded up to 64)
+    HSP_GLOBAL double* Linv;       // tile path, P x P: lower triangle holds L^-1 = U^-T
+    HSP_GLOBAL double* Dinv;       // ceil(p/64) x 64 x 64: inverses of U's diagonal blocks
+    HSP_GLOBAL double* vec;        // 2 p scratch
+    HSP_GLOBAL double* ring_beta;  // capacity x p
+    HSP_GLOBAL double* ring_tau;   // capacity
+    HSP_GLOBAL double* ring_lam;   // capacity x p or null
     uint32_t thin;
     uint32_t capacity;
-    Ctrl* ctrl;
+    HSP_GLOBAL Ctrl* ctrl;
     uint64_t seed;
     uint32_t chain;
     uint32_t mode;           // kMode* bits
@@ -103,10 +120,10 @@ struct SweepArgs {
     uint32_t gz;             // z-pass blocks (after the group)
     uint32_t zgroups;        // ceil(gz / kZGroup)
     uint64_t timeout_ticks;  // bound of every wait, in s_memrealtime ticks
-    uint64_t* trace;         // optional: kTraceSlots timestamps per group block
-    const uint32_t* tasks;   // tile path: every group block's task list, concatenated
-    const uint32_t* task_off;  // gp + 1 offsets into tasks
-    uint32_t* ver;           // tile path: 2 x nt x nt tile version counters (zero between launches)
+    HSP_GLOBAL uint64_t* trace;         // optional: kTraceSlots timestamps per group block
+    HSP_GLOBAL const uint32_t* tasks;   // tile path: every group block's task list, concatenated
+    HSP_GLOBAL const uint32_t* task_off;  // gp + 1 offsets into tasks
+    HSP_GLOBAL uint32_t* ver;           // tile path: 2 x nt x nt tile version counters (zero between launches)
 };
 
 // Diagnostic trace per group block: slot 0 = start, slots 1.. one value per

@@ -58,11 +58,20 @@ __device__ __forceinline__ bool group_failed(const Group& g, double* lds_flag) {
     return f;
 }
 
+// Sleep about 64 * n cycles between polls.  Polls are coherent loads that
+// bypass the L2 and all land on one memory channel: a tight loop from many
+// blocks slows the z pass's stream, so every wait backs off exponentially.
+__device__ __forceinline__ void backoff(uint32_t& n, uint32_t cap) {
+    for (uint32_t i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(1);
+    n = n < cap ? 2 * n : cap;
+}
+
 // Thread 0 only: wait until *ctr >= target, or give up after the timeout.
 // Relaxed polls; the caller orders its later reads with one acquire fence.
 __device__ __forceinline__ void wait_count(unsigned long long* ctr, unsigned long long target,
-                                        Ctrl* ctrl, uint64_t timeout) {
+                                        Ctrl* ctrl, uint64_t timeout, uint32_t cap = 16) {
     const uint64_t t0 = wall_clock64();
+    uint32_t nap = 1;
     while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         if (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrTimeout)
             break;
@@ -70,7 +79,7 @@ __device__ __forceinline__ void wait_count(unsigned long long* ctr, unsigned lon
             atomicOr(&ctrl->err, kErrTimeout);
             break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        backoff(nap, cap);
     }
 }
 
@@ -79,6 +88,19 @@ __device__ __forceinline__ void wait_count(unsigned long long* ctr, unsigned lon
 // after observing, one thread invalidates (acquire) before the block reads.
 __device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// Tiles that the factorisation's tasks hand to each other move through
+// device-coherent loads and stores (they bypass the non-coherent caches), so
+// a task needs no cache writeback or invalidate: its stores are complete once
+// every wave has waited for them, and the version it then publishes orders
+// them for the reader.  Fences here would flush or drop a whole XCD's L2 and
+// stall the z pass streaming through it.
+__device__ __forceinline__ double ldc(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stc(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Thread 0: next trace timestamp, or a given value (diagnostics only).
 __device__ __forceinline__ void stamp(Group& g) {
@@ -95,10 +117,11 @@ __device__ __forceinline__ void stamp_at(uint64_t* rec, int s) {
 
 // Thread 0 only: wait until *v[i] >= need[i] for i < n (the n loads of a poll
 // are in flight together); false if the group is failing or the wait timed
-// out.  Relaxed polls: the caller follows a success with fence_acquire().
+// out.  The tiles read after a success are loaded coherently (ldc).
 __device__ __forceinline__ bool wait_vers(uint32_t* const (&v)[3], const uint32_t (&need)[3], int n,
                                           Ctrl* ctrl, uint64_t timeout) {
     uint64_t t0 = 0;
+    uint32_t nap = 1;
     for (int it = 0;; ++it) {
         uint32_t got[3];
 #pragma unroll
@@ -116,19 +139,17 @@ __device__ __forceinline__ bool wait_vers(uint32_t* const (&v)[3], const uint32_
             atomicOr(&ctrl->err, kErrTimeout);
             return false;
         }
-        __builtin_amdgcn_s_sleep(1);
+        backoff(nap, 8);
     }
 }
 
-// Make this block's global stores visible device-wide, then set *ver = val
-// (and *ver2 = val2): every wave waits for its own stores, one thread writes
-// the cache back and publishes.
+// Publish *ver = val (and *ver2 = val2) once this block's coherent tile
+// stores are complete: every wave waits for its own stores first.
 __device__ __forceinline__ void publish(uint32_t* ver, uint32_t val, uint32_t* ver2 = nullptr,
                                         uint32_t val2 = 0) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        fence_release();
         __hip_atomic_store(ver, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (ver2) __hip_atomic_store(ver2, val2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -352,7 +373,7 @@ __device__ void small_path(const SweepArgs& a, Group& g, uint32_t k, double* lds
     }
     if (a.mode & kModeZ) {
         if (threadIdx.x == 0) {
-            wait_count(&a.ctrl->z_count, g.zbase + a.zgroups, a.ctrl, a.timeout_ticks);
+            wait_count(&a.ctrl->z_count, g.zbase + a.zgroups, a.ctrl, a.timeout_ticks, 64);
             fence_acquire();
         }
         __syncthreads();
@@ -427,7 +448,7 @@ __device__ __forceinline__ void load_tile(Tile& T, const double* M, uint32_t P, 
     const double* src = M + (size_t)(r0 + rb) * P + c0 + c;
     double v[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = src[(size_t)(4 * q) * P];
+    for (int q = 0; q < 16; ++q) v[q] = ldc(src + (size_t)(4 * q) * P);
     if (add_diag) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
@@ -449,8 +470,8 @@ __device__ __forceinline__ void load_tiles(Tile& S, const double* MS, uint32_t r
     double v[16], w[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        v[q] = s0[(size_t)(4 * q) * P];
-        w[q] = t0[(size_t)(4 * q) * P];
+        v[q] = ldc(s0 + (size_t)(4 * q) * P);
+        w[q] = ldc(t0 + (size_t)(4 * q) * P);
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -513,7 +534,7 @@ __device__ __forceinline__ void load_tile_m(MTile& o, const double* M, uint32_t 
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                o.v[bi][bj][r] = M ? M[(size_t)(ri + 16 * bi + 4 * r) * P + cj + 16 * bj] : 0.0;
+                o.v[bi][bj][r] = M ? ldc(M + (size_t)(ri + 16 * bi + 4 * r) * P + cj + 16 * bj) : 0.0;
     if (add_diag) {
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
@@ -545,7 +566,7 @@ __device__ __forceinline__ void put_tile_m(double* M, uint32_t P, uint32_t r0, u
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) M[(size_t)(ri + 16 * bi + 4 * r) * P + cj + 16 * bj] = out[bi][bj][r];
+            for (int r = 0; r < 4; ++r) stc(M + (size_t)(ri + 16 * bi + 4 * r) * P + cj + 16 * bj, out[bi][bj][r]);
 }
 
 // X = old + sign * acc in LDS (the matrix-core layout, X's own rows and columns).
@@ -681,9 +702,9 @@ __device__ void diag_factor(const SweepArgs& a, uint32_t kb, Tile& S, Tile& T, u
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int r = rb + 4 * q;
-            a.A[(size_t)(k0 + r) * P + k0 + c] = S[r][c];
-            D[r * kTile + c] = T[c][r];
-            a.Linv[(size_t)(k0 + r) * P + k0 + c] = T[r][c];
+            stc(a.A + (size_t)(k0 + r) * P + k0 + c, S[r][c]);
+            stc(D + r * kTile + c, T[c][r]);
+            stc(a.Linv + (size_t)(k0 + r) * P + k0 + c, T[r][c]);
         }
     } else if (threadIdx.x == 0) {
         atomicOr(&a.ctrl->err, kErrNotPD);
@@ -751,7 +772,6 @@ __device__ bool run_tasks(const SweepArgs& a, Group& g, uint32_t rank, double ta
             }
             const bool w = wait_vers(v, need, nv, a.ctrl, g.timeout);
             *flag = w ? 0.0 : 1.0;
-            fence_acquire();
         }
         __syncthreads();
         stamp_value(g, n + 1u);
@@ -810,8 +830,8 @@ __device__ bool run_tasks(const SweepArgs& a, Group& g, uint32_t rank, double ta
             double v[16], x[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
-                v[q] = Dk[(rb + 4 * q) * kTile + c];
-                x[q] = src[(size_t)(4 * q) * P];
+                v[q] = ldc(Dk + (rb + 4 * q) * kTile + c);
+                x[q] = ldc(src + (size_t)(4 * q) * P);
             }
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
@@ -882,7 +902,7 @@ __device__ void tile_path(const SweepArgs& a, Group& g, uint32_t rank, uint32_t 
 
     if (a.mode & kModeZ) {
         if (threadIdx.x == 0) {
-            wait_count(&a.ctrl->z_count, g.zbase + a.zgroups, a.ctrl, a.timeout_ticks);
+            wait_count(&a.ctrl->z_count, g.zbase + a.zgroups, a.ctrl, a.timeout_ticks, 64);
             fence_acquire();
         }
         if (g.trace && threadIdx.x == 0) g.trace[kTraceSlots - 1] = wall_clock64();
