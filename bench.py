@@ -13,6 +13,8 @@ Prints one JSON line.  Also reports:
                 against the 8 TB/s HBM peak; traffic = hardware-counted HBM
                 bytes per launch when the stored counter reading matches the
                 current kernel sources
+  read_ceiling  a plain streaming read of the same X (16-byte non-temporal
+                loads, nothing else) on this GPU: what the z pass could reach
   cpu_baseline  the float64 oracle timed on this host on a bounded sample of
                 the same workload (whole sweeps, one thread)
 """
@@ -129,6 +131,7 @@ def main():
     zpass_ms, sweep_ms, n_timed = s.timing()
     clamps, maxatt = s.counters()
     s.set_timing(False)
+    ceil_ms, ceil_bytes = hsp.hsp_read_ceiling(s.h, 10)
     print(f"[bench] {a.steps} sweeps in {elapsed:.3f}s; sweep kernel {zpass_ms:.4f} ms per launch, "
           f"{sweep_ms:.4f} ms per sweep (events)", file=sys.stderr, flush=True)
 
@@ -165,6 +168,9 @@ def main():
         "kernel_ms": round(zpass_ms, 5),
         "sweep_ms_events": round(sweep_ms, 5),
         "kernel_fingerprint": kernel_fingerprint(),
+        "read_ceiling": {"gbps": round(ceil_bytes / (ceil_ms * 1e-3) / 1e9, 1),
+                         "ms_per_pass": round(ceil_ms, 5),
+                         "kernel": "plain 16-byte non-temporal streaming read of the same X"},
         "max_tn_proposals": int(maxatt),
         "lambda_clamps": int(clamps),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,

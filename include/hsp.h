@@ -206,6 +206,14 @@ hsp_status hsp_get_phase_trace(hsp_state* s, uint64_t* out, int64_t* group_block
 hsp_status hsp_tile_schedule(int64_t nt, int64_t gp, uint32_t* tasks, int64_t cap, uint32_t* off,
                              int64_t* n_tasks);
 
+/* Read ceiling of this GPU for the state's design: the mean milliseconds of
+ * one pass of a plain streaming read (16-byte non-temporal loads, nothing
+ * else) over the library's copy of X (N x ld elements), over `iters` passes
+ * after two untimed ones, timed with HIP events on the state's stream.  The
+ * z pass reads the same bytes; this bounds what it can reach.  Synchronises.
+ * Errors: HSP_EINVAL if iters < 1; HSP_EPOISONED; HSP_EHIP. */
+hsp_status hsp_read_ceiling(hsp_state* s, int32_t iters, double* ms_per_pass, double* bytes_per_pass);
+
 /* Philox4x32-10 on the device: out[4i..4i+3] = Philox(ctr[4i..4i+3], key =
  * seed).  ctr and out are host arrays of 4n words.  Test hook for the
  * generator's bit-exactness. */

@@ -662,6 +662,32 @@ hsp_status hsp_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* o
     return HSP_OK;
 }
 
+hsp_status hsp_read_ceiling(hsp_state* s, int32_t iters, double* ms_per_pass, double* bytes_per_pass) {
+    if (!s || iters < 1 || !ms_per_pass) return s ? fail(s, HSP_EINVAL, "bad arguments") : HSP_EINVAL;
+    if (s->poisoned) return HSP_EPOISONED;
+    const size_t esz = s->x.xtype == 0 ? 4 : 2;
+    const size_t bytes = (size_t)s->x.N * s->x.ld * esz;
+    float* sink = nullptr;
+    HIP_TRY(dalloc(&sink, 1));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (!e) e = hipEventCreate(&e1);
+    for (int w = 0; !e && w < 2; ++w) e = stream_read_launch(s->Xbuf, bytes, s->num_cus, sink, s->stream);
+    if (!e) e = hipEventRecord(e0, s->stream);
+    for (int i = 0; !e && i < iters; ++i) e = stream_read_launch(s->Xbuf, bytes, s->num_cus, sink, s->stream);
+    if (!e) e = hipEventRecord(e1, s->stream);
+    if (!e) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (!e) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(sink);
+    HIP_TRY(e);
+    *ms_per_pass = ms / iters;
+    if (bytes_per_pass) *bytes_per_pass = (double)bytes;
+    return HSP_OK;
+}
+
 hsp_status hsp_tile_schedule(int64_t nt, int64_t gp, uint32_t* tasks, int64_t cap, uint32_t* off,
                              int64_t* n_tasks) {
     if (nt < 1 || nt > kMaxP / kTile || gp < 1 || gp > 4096 || !n_tasks)

@@ -156,6 +156,38 @@ hipError_t pad_gram_launch(const double* G, uint32_t p, uint32_t P, double* Gp, 
     return hipGetLastError();
 }
 
+// Read ceiling: stream `bytes` (a multiple of 16) with eight 16-byte
+// non-temporal loads in flight per lane, grid-stride, the same kind of load
+// as the z pass, and nothing else.
+typedef unsigned int RdVec __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void stream_read_kernel(const RdVec* __restrict__ x, size_t n16,
+                                                          float* __restrict__ sink) {
+    constexpr int kUnroll = 8;
+    float s = 0.0f;
+    size_t i = (size_t)blockIdx.x * 256 * kUnroll + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * 256 * kUnroll;
+    for (; i + 256 * (kUnroll - 1) < n16; i += stride) {
+        RdVec v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) v[u] = __builtin_nontemporal_load(x + i + 256 * u);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) s += __uint_as_float(v[u].x ^ v[u].y ^ v[u].z ^ v[u].w);
+    }
+    for (; i < n16; i += 256) {  // the ragged end, one load at a time
+        const RdVec v = __builtin_nontemporal_load(x + i);
+        s += __uint_as_float(v.x ^ v.y ^ v.z ^ v.w);
+    }
+    if (s == -1.0f) sink[0] = s;  // never true for the sums of finite data; keeps the loads
+}
+
+hipError_t stream_read_launch(const void* x, size_t bytes, int num_cus, float* sink, hipStream_t st) {
+    const size_t n16 = bytes / 16;
+    const unsigned blocks = (unsigned)(2 * num_cus);
+    hipLaunchKernelGGL(stream_read_kernel, dim3(blocks), dim3(256), 0, st,
+                       static_cast<const RdVec*>(x), n16, sink);
+    return hipGetLastError();
+}
+
 hipError_t philox_test_launch(uint64_t seed, const uint32_t* ctr, uint32_t n, uint32_t* out,
                               hipStream_t st) {
     hipLaunchKernelGGL(philox_test_kernel, dim3((n + 255) / 256), dim3(256), 0, st, seed, ctr, n, out);

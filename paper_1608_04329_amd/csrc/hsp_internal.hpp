@@ -182,6 +182,9 @@ hipError_t validate_launch(const XLayout& x, const uint8_t* y, Ctrl* ctrl, hipSt
 // library layout.
 hipError_t pack_x_launch(const float* src, const XLayout& dst, hipStream_t st);
 
+// Stream `bytes` of x with plain 16-byte loads only (the read ceiling).
+hipError_t stream_read_launch(const void* x, size_t bytes, int num_cus, float* sink, hipStream_t st);
+
 hipError_t philox_test_launch(uint64_t seed, const uint32_t* ctr, uint32_t n, uint32_t* out,
                               hipStream_t st);
 

@@ -27,7 +27,7 @@ EXPORTS = ["hsp_default_options", "hsp_max_p", "hsp_create", "hsp_sweep", "hsp_s
            "hsp_destroy", "hsp_last_error", "hsp_get_state", "hsp_set_state", "hsp_step",
            "hsp_get_debug", "hsp_get_gram", "hsp_get_counters", "hsp_set_timing",
            "hsp_get_timing", "hsp_philox", "hsp_set_phase_trace", "hsp_get_phase_trace",
-           "hsp_tile_schedule"]
+           "hsp_tile_schedule", "hsp_read_ceiling"]
 
 
 class hsp_options(C.Structure):
@@ -83,6 +83,8 @@ def load():
     L.hsp_get_phase_trace.restype = st
     L.hsp_tile_schedule.argtypes = [i64, i64, vp, i64, vp, C.POINTER(i64)]
     L.hsp_tile_schedule.restype = st
+    L.hsp_read_ceiling.argtypes = [vp, i32, C.POINTER(d), C.POINTER(d)]
+    L.hsp_read_ceiling.restype = st
     _lib = L
     return L
 
@@ -207,6 +209,13 @@ def hsp_tile_schedule(nt, gp):
     off = np.zeros(3, np.uint32)
     _check(load().hsp_tile_schedule(nt, gp, _hp(tasks), tasks.size, _hp(off), C.byref(n)))
     return tasks[: n.value], off[: 2 if gp == 1 else 3]
+
+
+def hsp_read_ceiling(h, iters=10):
+    """(ms per pass, bytes per pass) of a plain streaming read of the state's X."""
+    ms, nb = C.c_double(), C.c_double()
+    _check(load().hsp_read_ceiling(h, iters, C.byref(ms), C.byref(nb)), h)
+    return ms.value, nb.value
 
 
 def hsp_set_phase_trace(h, enable):
