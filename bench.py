@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "sweep_kernel_traffic.json"))
+    ap.add_argument("--batch", action="store_true",
+                    help="the batched form instead: 64 uneven float32 datasets (one chain each) "
+                         "and 16 chains sharing the N=1e6, p=1000 design in bfloat16; reports "
+                         "chain-sweeps/s batched and plain")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device twice (a plain copy kernel of known "
                          "size, to scale hardware byte counters)")
@@ -85,12 +89,75 @@ def cpu_baseline(d, seconds):
                       f"(untimed)"}
 
 
+def run_batch(a):
+    """Chain-sweeps/s of the batched form against the same chains swept one by one."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1608_04329_amd import hsp
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    shapes = synth.batch_shapes(64, seed=1000)
+    ds = [synth.batch_dataset(k, N, p) for k, (N, p) in enumerate(shapes)]
+    beta_true, _ = synth.sparse_beta(1000, 10, 13)
+    big = synth.probit_design(1_000_000, 1000, beta_true, 13, True, "n1000000_p1000")
+    print(f"[bench] batch data generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    datasets = [(torch.from_numpy(d.X).cuda(), torch.from_numpy(d.y).cuda(), "f32") for d in ds]
+    datasets.append((torch.from_numpy(big.X).cuda(), torch.from_numpy(big.y).cuda(), "bf16"))
+    counts = [1] * len(ds) + [16]
+    b = hsp.Batch(datasets, counts, seed=1, max_draws=64)
+    del datasets
+    torch.cuda.empty_cache()
+    nchains = len(b)
+    b.sweep(a.warmup)
+    b.sync()
+    b.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.sweep(a.steps)
+    b.sync()
+    elapsed = time.perf_counter() - t0
+    ms_ev, _ = b.timing()
+    b.set_timing(False)
+    batched = nchains * a.steps / elapsed
+    print(f"[bench] batched: {a.steps} sweeps of {nchains} chains in {elapsed:.3f}s "
+          f"({ms_ev:.3f} ms per batched sweep by events)", file=sys.stderr, flush=True)
+    # plain: every chain swept on its own, one after another
+    t0 = time.perf_counter()
+    for c in b.chains:
+        c.sweep(a.steps)
+    for c in b.chains:
+        c.sync()
+    elapsed_plain = time.perf_counter() - t0
+    plain = nchains * a.steps / elapsed_plain
+    out = {
+        "metric": "chain-sweeps/sec, batched vs plain",
+        "value": round(batched, 1),
+        "unit": "chain-sweeps/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(1e3 * elapsed / a.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
+        "data": "synthetic",
+        "config": {"workload": "horseshoe_probit_batch_64uneven_f32_plus_16chains_N1e6_p1000_bf16",
+                   "chains": nchains, "datasets": len(ds) + 1},
+        "plain_chain_sweeps_per_s": round(plain, 1),
+        "batched_over_plain": round(batched / plain, 3),
+    }
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the row-sharded design is described in DESIGN.md).", file=sys.stderr)
         sys.exit(2)
+    if a.batch:
+        run_batch(a)
+        return
     import numpy as np
     import torch
 

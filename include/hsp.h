@@ -120,12 +120,58 @@ hsp_status hsp_sync(hsp_state* s);
 hsp_status hsp_draws(hsp_state* s, double* beta, double* tau_m2, double* lam_m2,
                      int64_t first, int64_t count, int64_t* n_out);
 
-/* Release every resource of the state (waits for its work first). */
+/* Release every resource of the state (waits for its work first).  A chain
+ * of a batch is released with its batch (HSP_EINVAL here). */
 hsp_status hsp_destroy(hsp_state* s);
 
 /* Text of the last failure on this state (never NULL); for a NULL state,
  * the last failure of hsp_create on this thread. */
 const char* hsp_last_error(const hsp_state* s);
+
+/* ---- Batches: many independent chains, one graph launch per sweep ----------
+ * A batch runs chains of the same sweep on several designs at once (the
+ * chains of one design share its library copy of X, y and G = X^T X).  One
+ * hsp_batch_sweep advances every chain by the same number of sweeps; each
+ * batched sweep is a single replay of a captured HIP graph holding every
+ * chain's sweep kernel, one after another on the batch's stream.  Chain i
+ * (dataset-major order) uses Philox counter word 3 = opt->chain_id + i, so it
+ * draws exactly what a lone sampler created with that chain id draws. */
+typedef struct hsp_batch hsp_batch; /* opaque, owned by the library */
+
+typedef struct {
+    const float* X;   /* N x p float32, row-major (device, or host if x_on_host) */
+    const uint8_t* y; /* N bytes, each 0 or 1 */
+    int64_t N;
+    int64_t p;
+    int32_t x_type;   /* storage of this X: HSP_X_F32 or HSP_X_BF16 */
+} hsp_dataset;
+
+/* Create chains_per_ds[d] chains on each of the n_ds datasets (read during
+ * the call only, as in hsp_create).  opt gives the options of every chain
+ * (its x_type is ignored: each dataset states its own; its hip_stream, if
+ * set, is the batch's stream).  Errors: as hsp_create for any dataset;
+ * HSP_EINVAL if n_ds < 1, a count is < 1 or the total exceeds 65536. */
+hsp_status hsp_batch_create(const hsp_dataset* ds, int32_t n_ds, const int32_t* chains_per_ds,
+                            const hsp_options* opt, hsp_batch** out);
+/* Number of chains. */
+int64_t hsp_batch_size(const hsp_batch* b);
+/* A borrowed handle of chain i, valid until hsp_batch_destroy: every state
+ * entry point accepts it (hsp_draws, hsp_get_state, ...), hsp_destroy does not. */
+hsp_status hsp_batch_chain(hsp_batch* b, int64_t i, hsp_state** chain);
+/* Enqueue n_iter sweeps of every chain and return without waiting.
+ * Errors: HSP_EINVAL if n_iter < 0; HSP_EPOISONED if a chain is poisoned; HSP_EHIP. */
+hsp_status hsp_batch_sweep(hsp_batch* b, int64_t n_iter);
+/* Wait for the batch's work and report the first chain's device failure. */
+hsp_status hsp_batch_sync(hsp_batch* b);
+/* Timing of the batched sweeps enqueued while enabled (HIP events on the
+ * batch's stream around each graph replay): mean ms per batched sweep. */
+hsp_status hsp_batch_set_timing(hsp_batch* b, int32_t enable);
+hsp_status hsp_batch_get_timing(hsp_batch* b, double* ms_per_sweep, int64_t* n_sweeps);
+/* Text of the batch's last failure (never NULL; NULL batch: the last failed
+ * creation on this thread). */
+const char* hsp_batch_last_error(const hsp_batch* b);
+/* Release the batch and all its chains (waits for its work first). */
+hsp_status hsp_batch_destroy(hsp_batch* b);
 
 /* ---- Markov state: checkpoint / resume and test hooks --------------------- */
 /* Copy the Markov state to host buffers (beta, lam_m2, nu_m1: p doubles;

@@ -4,4 +4,4 @@ The sampler itself is the HIP library libhsp.so behind the C ABI of
 include/hsp.h; this package holds its sources (csrc/), its build script and a
 thin ctypes binding (hsp.py).
 """
-from .hsp import Sampler, HspError, load  # noqa: F401
+from .hsp import Batch, Sampler, HspError, load  # noqa: F401

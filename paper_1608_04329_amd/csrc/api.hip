@@ -46,6 +46,8 @@ struct hsp_state {
     hipGraphExec_t graph = nullptr;  // one whole sweep (one kernel), recording
     uint64_t* trace = nullptr;        // p-side phase timestamps (diagnostics)
     SweepArgs* dargs = nullptr;       // [0]: a whole sweep, [1]: the last hsp_step
+    const hsp_state* owner = nullptr;  // batch chain: X, y, G, Gp belong to this state
+    bool in_batch = false;             // owned by an hsp_batch (not destroyed alone)
     bool timing = false;
     std::vector<hipEvent_t> ev;  // per timed sweep: start, end
     int64_t timed_sweeps = 0;
@@ -182,6 +184,12 @@ void free_state(hsp_state* s) {
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    if (s->owner) {  // borrowed from the dataset's first chain
+        s->Xbuf = nullptr;
+        s->y = nullptr;
+        s->G = nullptr;
+        s->Gp = nullptr;
+    }
     void* bufs[] = {s->Xbuf, s->y, s->ctrl, s->beta, s->lam, s->nu, s->tau, s->xi, s->b, s->G, s->Gp,
                     s->A, s->Linv, s->Dinv, s->vec, s->partial, s->beta32, s->zdbg, s->adbg,
                     s->ring_beta, s->ring_tau, s->ring_lam, s->trace, s->gpartial,
@@ -219,7 +227,10 @@ hsp_status set_counters(hsp_state* s, uint64_t sweep) {
     return HSP_OK;
 }
 
-hsp_status create_impl(hsp_state* s, const float* X, const uint8_t* y, int64_t N, int64_t p) {
+hsp_status chain_impl(hsp_state* s);
+
+// Device, stream and wait bound of a new state.
+hsp_status setup_impl(hsp_state* s) {
     HIP_TRY(hipGetDevice(&s->device));
     HIP_TRY(hipDeviceGetAttribute(&s->num_cus, hipDeviceAttributeMultiprocessorCount, s->device));
     {
@@ -235,6 +246,12 @@ hsp_status create_impl(hsp_state* s, const float* X, const uint8_t* y, int64_t N
         HIP_TRY(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
         s->own_stream = true;
     }
+    return HSP_OK;
+}
+
+hsp_status create_impl(hsp_state* s, const float* X, const uint8_t* y, int64_t N, int64_t p) {
+    hsp_status st0 = setup_impl(s);
+    if (st0) return st0;
     const int xt = s->opt.x_type;
     const uint32_t align = xt == HSP_X_F32 ? 4 : 8;
     const uint32_t ld = (uint32_t)((p + align - 1) / align * align);
@@ -275,27 +292,10 @@ hsp_status create_impl(hsp_state* s, const float* X, const uint8_t* y, int64_t N
                         "y must hold only 0/1 and X must be finite (also after bfloat16 rounding)");
     }
 
-    // p-sized state
-    HIP_TRY(dalloc(&s->beta, p));
-    HIP_TRY(dalloc(&s->beta32, ld));
-    HIP_TRY(dalloc(&s->lam, p));
-    HIP_TRY(dalloc(&s->nu, p));
-    HIP_TRY(dalloc(&s->tau, 1));
-    HIP_TRY(dalloc(&s->xi, 1));
-    HIP_TRY(dalloc(&s->b, p));
+    // G = X^T X (and Gp for the tiled path), shared by every chain of this data
     HIP_TRY(dalloc(&s->G, (size_t)p * p));
     const size_t P = ((size_t)p + kTile - 1) / kTile * kTile;
-    if (p > kSmallP) {
-        HIP_TRY(dalloc(&s->Gp, P * P));
-        HIP_TRY(dalloc(&s->A, P * P));
-        HIP_TRY(dalloc(&s->Linv, P * P));
-        HIP_TRY(dalloc(&s->Dinv, P * kTile));
-        HIP_TRY(hipMemsetAsync(s->A, 0, P * P * sizeof(double), s->stream));
-        HIP_TRY(hipMemsetAsync(s->Linv, 0, P * P * sizeof(double), s->stream));
-    }
-    HIP_TRY(dalloc(&s->vec, 2 * (size_t)p + 8));
-
-    // G = X^T X
+    if (p > kSmallP) HIP_TRY(dalloc(&s->Gp, P * P));
     {
         double* work = nullptr;
         HIP_TRY(dalloc(&work, gram_work_doubles(s->x, s->num_cus)));
@@ -305,6 +305,46 @@ hsp_status create_impl(hsp_state* s, const float* X, const uint8_t* y, int64_t N
         (void)hipFree(work);
         HIP_TRY(e);
     }
+    return chain_impl(s);
+}
+
+// A further chain on the data of `owner` (same X, y, G; its own Markov state,
+// draw ring, factorisation buffers and control block).
+hsp_status clone_impl(hsp_state* s, const hsp_state* owner) {
+    hsp_status st0 = setup_impl(s);
+    if (st0) return st0;
+    s->owner = owner;
+    s->x = owner->x;
+    s->Xbuf = owner->Xbuf;
+    s->y = owner->y;
+    s->G = owner->G;
+    s->Gp = owner->Gp;
+    HIP_TRY(dalloc(&s->ctrl, 1));
+    HIP_TRY(hipMemsetAsync(s->ctrl, 0, sizeof(Ctrl), s->stream));
+    return chain_impl(s);
+}
+
+// Everything one chain owns, its launch plan, and the cold start.
+hsp_status chain_impl(hsp_state* s) {
+    const int64_t N = s->x.N, p = s->x.p;
+    const uint32_t ld = s->x.ld;
+    // p-sized state
+    HIP_TRY(dalloc(&s->beta, p));
+    HIP_TRY(dalloc(&s->beta32, ld));
+    HIP_TRY(dalloc(&s->lam, p));
+    HIP_TRY(dalloc(&s->nu, p));
+    HIP_TRY(dalloc(&s->tau, 1));
+    HIP_TRY(dalloc(&s->xi, 1));
+    HIP_TRY(dalloc(&s->b, p));
+    const size_t P = ((size_t)p + kTile - 1) / kTile * kTile;
+    if (p > kSmallP) {
+        HIP_TRY(dalloc(&s->A, P * P));
+        HIP_TRY(dalloc(&s->Linv, P * P));
+        HIP_TRY(dalloc(&s->Dinv, P * kTile));
+        HIP_TRY(hipMemsetAsync(s->A, 0, P * P * sizeof(double), s->stream));
+        HIP_TRY(hipMemsetAsync(s->Linv, 0, P * P * sizeof(double), s->stream));
+    }
+    HIP_TRY(dalloc(&s->vec, 2 * (size_t)p + 8));
 
     HIP_TRY(sweep_plan(s->x, s->num_cus, &s->plan));
     if (p > kSmallP) {
@@ -412,6 +452,195 @@ hsp_status hsp_create(const float* X, const uint8_t* y, int64_t N, int64_t p,
     return HSP_OK;
 }
 
+// ---- batches: many chains, one graph launch per sweep ------------------------------
+}  // extern "C"
+
+struct hsp_batch {
+    std::vector<hsp_state*> chains;  // dataset-major; the first chain of each dataset owns its data
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipGraphExec_t graph = nullptr;  // every chain's sweep, one after another
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // per timed batched sweep: start, end
+    std::string err;
+};
+
+namespace {
+
+void free_batch(hsp_batch* b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+    for (auto it = b->chains.rbegin(); it != b->chains.rend(); ++it) free_state(*it);  // borrowers first
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+hsp_status batch_fail(hsp_batch* b, hsp_status code, const std::string& msg) {
+    if (b) b->err = msg;
+    return code;
+}
+
+}  // namespace
+
+extern "C" {
+
+hsp_status hsp_batch_create(const hsp_dataset* ds, int32_t n_ds, const int32_t* chains_per_ds,
+                            const hsp_options* opt, hsp_batch** out) {
+    if (!out) return fail(nullptr, HSP_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (!ds || !chains_per_ds || n_ds < 1) return fail(nullptr, HSP_EINVAL, "bad batch description");
+    hsp_options base;
+    if (opt) base = *opt;
+    else hsp_default_options(&base);
+    int64_t total = 0;
+    for (int32_t d = 0; d < n_ds; ++d) {
+        if (chains_per_ds[d] < 1) return fail(nullptr, HSP_EINVAL, "every dataset needs at least one chain");
+        total += chains_per_ds[d];
+    }
+    if (total > 65536) return fail(nullptr, HSP_EINVAL, "at most 65536 chains per batch");
+    hsp_batch* b = new (std::nothrow) hsp_batch();
+    if (!b) return fail(nullptr, HSP_ENOMEM, "host allocation failed");
+    if (base.hip_stream) {
+        b->stream = static_cast<hipStream_t>(base.hip_stream);
+    } else if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return fail(nullptr, HSP_EHIP, "stream creation failed");
+    }
+    else {
+        b->own_stream = true;
+    }
+    uint32_t chain_id = base.chain_id;
+    for (int32_t d = 0; d < n_ds; ++d) {
+        hsp_state* owner = nullptr;
+        for (int32_t c = 0; c < chains_per_ds[d]; ++c, ++chain_id) {
+            hsp_options o = base;
+            o.hip_stream = b->stream;
+            o.x_type = ds[d].x_type;
+            o.chain_id = chain_id;
+            o.use_graph = 1;
+            hsp_state* s = nullptr;
+            hsp_status st;
+            if (c == 0) {
+                st = hsp_create(ds[d].X, ds[d].y, ds[d].N, ds[d].p, &o, &s);
+            } else {
+                s = new (std::nothrow) hsp_state();
+                if (!s) {
+                    st = fail(nullptr, HSP_ENOMEM, "host allocation failed");
+                } else {
+                    s->opt = o;
+                    st = clone_impl(s, owner);
+                    if (st != HSP_OK) {
+                        if (!s->err.empty()) g_create_error = s->err;
+                        free_state(s);
+                        s = nullptr;
+                    }
+                }
+            }
+            if (st != HSP_OK) {
+                free_batch(b);
+                return st;
+            }
+            s->in_batch = true;
+            if (c == 0) owner = s;
+            b->chains.push_back(s);
+        }
+    }
+    *out = b;
+    return HSP_OK;
+}
+
+int64_t hsp_batch_size(const hsp_batch* b) { return b ? (int64_t)b->chains.size() : 0; }
+
+hsp_status hsp_batch_chain(hsp_batch* b, int64_t i, hsp_state** chain) {
+    if (!b || !chain || i < 0 || i >= (int64_t)b->chains.size())
+        return batch_fail(b, HSP_EINVAL, "chain index out of range");
+    *chain = b->chains[(size_t)i];
+    return HSP_OK;
+}
+
+hsp_status hsp_batch_sweep(hsp_batch* b, int64_t n) {
+    if (!b) return HSP_EINVAL;
+    if (n < 0) return batch_fail(b, HSP_EINVAL, "n_iter must be >= 0");
+    for (hsp_state* s : b->chains) {
+        if (s->poisoned) return batch_fail(b, HSP_EPOISONED, "a chain of the batch is poisoned");
+        if (s->sweeps_done + (uint64_t)n >= (uint64_t(1) << 32) - 1)
+            return batch_fail(b, HSP_EINVAL, "the sweep counter would exceed 2^32");
+    }
+    if (!b->graph) {
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+        for (size_t i = 0; !e && i < b->chains.size(); ++i) e = enqueue_sweep(b->chains[i], b->stream);
+        hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+        if (!e) e = e2;
+        if (!e) e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e) return batch_fail(b, HSP_EHIP, std::string("batch graph capture: ") + hipGetErrorString(e));
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        hipEvent_t e2[2] = {nullptr, nullptr};
+        if (b->timing) {
+            for (auto& e : e2)
+                if (hipEventCreate(&e) != hipSuccess) return batch_fail(b, HSP_EHIP, "event creation");
+            b->ev.push_back(e2[0]);
+            b->ev.push_back(e2[1]);
+            if (hipEventRecord(e2[0], b->stream) != hipSuccess) return batch_fail(b, HSP_EHIP, "event record");
+        }
+        if (hipGraphLaunch(b->graph, b->stream) != hipSuccess)
+            return batch_fail(b, HSP_EHIP, "batch graph launch");
+        if (b->timing && hipEventRecord(e2[1], b->stream) != hipSuccess)
+            return batch_fail(b, HSP_EHIP, "event record");
+    }
+    for (hsp_state* s : b->chains) s->sweeps_done += (uint64_t)n;
+    return HSP_OK;
+}
+
+hsp_status hsp_batch_sync(hsp_batch* b) {
+    if (!b) return HSP_EINVAL;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return batch_fail(b, HSP_EHIP, "stream synchronisation");
+    for (size_t i = 0; i < b->chains.size(); ++i) {
+        hsp_status st = check_device_flags(b->chains[i]);
+        if (st != HSP_OK) return batch_fail(b, st, "chain " + std::to_string(i) + ": " + b->chains[i]->err);
+    }
+    return HSP_OK;
+}
+
+hsp_status hsp_batch_set_timing(hsp_batch* b, int32_t enable) {
+    if (!b) return HSP_EINVAL;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return batch_fail(b, HSP_EHIP, "stream synchronisation");
+    for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+    b->ev.clear();
+    b->timing = enable != 0;
+    return HSP_OK;
+}
+
+hsp_status hsp_batch_get_timing(hsp_batch* b, double* ms_per_sweep, int64_t* n) {
+    if (!b || !ms_per_sweep) return HSP_EINVAL;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return batch_fail(b, HSP_EHIP, "stream synchronisation");
+    const size_t ns = b->ev.size() / 2;
+    double sum = 0.0;
+    for (size_t i = 0; i < ns; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, b->ev[2 * i], b->ev[2 * i + 1]) != hipSuccess)
+            return batch_fail(b, HSP_EHIP, "event timing");
+        sum += ms;
+    }
+    *ms_per_sweep = ns ? sum / ns : 0.0;
+    if (n) *n = (int64_t)ns;
+    return HSP_OK;
+}
+
+const char* hsp_batch_last_error(const hsp_batch* b) {
+    return b ? b->err.c_str() : g_create_error.c_str();
+}
+
+hsp_status hsp_batch_destroy(hsp_batch* b) {
+    if (!b) return HSP_EINVAL;
+    free_batch(b);
+    return HSP_OK;
+}
+
 hsp_status hsp_sweep(hsp_state* s, int64_t n) {
     if (!s) return HSP_EINVAL;
     if (s->poisoned) return HSP_EPOISONED;
@@ -477,6 +706,7 @@ hsp_status hsp_draws(hsp_state* s, double* beta, double* tau_m2, double* lam_m2,
 }
 
 hsp_status hsp_destroy(hsp_state* s) {
+    if (s && s->in_batch) return fail(s, HSP_EINVAL, "this chain belongs to a batch: destroy the batch");
     free_state(s);
     return HSP_OK;
 }

@@ -27,7 +27,9 @@ EXPORTS = ["hsp_default_options", "hsp_max_p", "hsp_create", "hsp_sweep", "hsp_s
            "hsp_destroy", "hsp_last_error", "hsp_get_state", "hsp_set_state", "hsp_step",
            "hsp_get_debug", "hsp_get_gram", "hsp_get_counters", "hsp_set_timing",
            "hsp_get_timing", "hsp_philox", "hsp_set_phase_trace", "hsp_get_phase_trace",
-           "hsp_tile_schedule", "hsp_read_ceiling"]
+           "hsp_tile_schedule", "hsp_read_ceiling", "hsp_batch_create", "hsp_batch_size",
+           "hsp_batch_chain", "hsp_batch_sweep", "hsp_batch_sync", "hsp_batch_set_timing",
+           "hsp_batch_get_timing", "hsp_batch_last_error", "hsp_batch_destroy"]
 
 
 class hsp_options(C.Structure):
@@ -35,6 +37,11 @@ class hsp_options(C.Structure):
                 ("x_on_host", C.c_int32), ("record_lambda", C.c_int32), ("thin", C.c_int64),
                 ("max_draws", C.c_int64), ("hip_stream", C.c_void_p), ("debug_store_z", C.c_int32),
                 ("use_graph", C.c_int32)]
+
+
+class hsp_dataset(C.Structure):
+    _fields_ = [("X", C.c_void_p), ("y", C.c_void_p), ("N", C.c_int64), ("p", C.c_int64),
+                ("x_type", C.c_int32)]
 
 
 class HspError(RuntimeError):
@@ -85,6 +92,18 @@ def load():
     L.hsp_tile_schedule.restype = st
     L.hsp_read_ceiling.argtypes = [vp, i32, C.POINTER(d), C.POINTER(d)]
     L.hsp_read_ceiling.restype = st
+    L.hsp_batch_create.argtypes = [C.POINTER(hsp_dataset), i32, C.POINTER(i32), C.POINTER(hsp_options),
+                                   C.POINTER(vp)]
+    L.hsp_batch_create.restype = st
+    L.hsp_batch_size.argtypes = [vp]; L.hsp_batch_size.restype = i64
+    L.hsp_batch_chain.argtypes = [vp, i64, C.POINTER(vp)]; L.hsp_batch_chain.restype = st
+    L.hsp_batch_sweep.argtypes = [vp, i64]; L.hsp_batch_sweep.restype = st
+    L.hsp_batch_sync.argtypes = [vp]; L.hsp_batch_sync.restype = st
+    L.hsp_batch_set_timing.argtypes = [vp, i32]; L.hsp_batch_set_timing.restype = st
+    L.hsp_batch_get_timing.argtypes = [vp, C.POINTER(d), C.POINTER(i64)]
+    L.hsp_batch_get_timing.restype = st
+    L.hsp_batch_last_error.argtypes = [vp]; L.hsp_batch_last_error.restype = C.c_char_p
+    L.hsp_batch_destroy.argtypes = [vp]; L.hsp_batch_destroy.restype = st
     _lib = L
     return L
 
@@ -136,7 +155,7 @@ def hsp_draws(h, first, count, p, lam=False):
 
 
 def hsp_destroy(h):
-    load().hsp_destroy(h)
+    _check(load().hsp_destroy(h), h)
 
 
 def hsp_get_state(h, p):
@@ -218,6 +237,54 @@ def hsp_read_ceiling(h, iters=10):
     return ms.value, nb.value
 
 
+def _bcheck(code, b=None):
+    if code != HSP_OK:
+        msg = load().hsp_batch_last_error(b)
+        raise HspError(code, msg.decode() if msg else "")
+
+
+def hsp_batch_create(datasets, chains_per_ds, opt=None):
+    """datasets: list of (X pointer, y pointer, N, p, x_type); pointers as for hsp_create."""
+    arr = (hsp_dataset * len(datasets))(*[hsp_dataset(X, y, N, p, xt) for X, y, N, p, xt in datasets])
+    cnt = (C.c_int32 * len(chains_per_ds))(*chains_per_ds)
+    b = C.c_void_p()
+    _bcheck(load().hsp_batch_create(arr, len(datasets), cnt, C.byref(opt) if opt is not None else None,
+                                    C.byref(b)))
+    return b
+
+
+def hsp_batch_size(b):
+    return load().hsp_batch_size(b)
+
+
+def hsp_batch_chain(b, i):
+    h = C.c_void_p()
+    _bcheck(load().hsp_batch_chain(b, i, C.byref(h)), b)
+    return h
+
+
+def hsp_batch_sweep(b, n):
+    _bcheck(load().hsp_batch_sweep(b, n), b)
+
+
+def hsp_batch_sync(b):
+    _bcheck(load().hsp_batch_sync(b), b)
+
+
+def hsp_batch_set_timing(b, enable):
+    _bcheck(load().hsp_batch_set_timing(b, int(enable)), b)
+
+
+def hsp_batch_get_timing(b):
+    ms, n = C.c_double(), C.c_int64()
+    _bcheck(load().hsp_batch_get_timing(b, C.byref(ms), C.byref(n)), b)
+    return ms.value, n.value
+
+
+def hsp_batch_destroy(b):
+    _bcheck(load().hsp_batch_destroy(b))
+
+
 def hsp_set_phase_trace(h, enable):
     _check(load().hsp_set_phase_trace(h, int(enable)), h)
 
@@ -270,7 +337,17 @@ class Sampler:
         self.record_lambda = record_lambda
         self.h = hsp_create(xp, yp, self.N, self.p, opt)
 
+    @classmethod
+    def _borrowed(cls, h, N, p, record_lambda, keep):
+        """A view of a batch's chain (released with the batch)."""
+        s = cls.__new__(cls)
+        s.h, s.N, s.p, s.record_lambda, s._batch = h, N, p, record_lambda, keep
+        return s
+
     def close(self):
+        if getattr(self, "_batch", None) is not None:
+            self.h = None  # owned by the batch
+            return
         if self.h:
             hsp_destroy(self.h)
             self.h = None
@@ -316,3 +393,87 @@ class Sampler:
 
     def timing(self):
         return hsp_get_timing(self.h)
+
+
+class Batch:
+    """Many independent chains, advanced together by one graph replay per sweep.
+
+    datasets: list of (X, y) or (X, y, x_type) with X, y as for Sampler (all on
+    the GPU, or all numpy); chains: chains per dataset (an int for all).
+    Chain i (dataset-major) uses chain id chain_id + i.
+    """
+
+    def __init__(self, datasets, chains=1, seed=1, chain_id=0, record_lambda=False, thin=1,
+                 max_draws=1024, stream=None):
+        load()
+        opt = hsp_default_options()
+        opt.seed = seed
+        opt.chain_id = chain_id
+        opt.record_lambda = int(record_lambda)
+        opt.thin = thin
+        opt.max_draws = max_draws
+        if stream is not None:
+            opt.hip_stream = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        counts = [chains] * len(datasets) if isinstance(chains, int) else list(chains)
+        descs, self._keep, shapes = [], [], []
+        host = None
+        for ds in datasets:
+            X, y = ds[0], ds[1]
+            xt = {"f32": HSP_X_F32, "bf16": HSP_X_BF16}[ds[2] if len(ds) > 2 else "f32"]
+            if isinstance(X, np.ndarray):
+                X = np.ascontiguousarray(X, np.float32)
+                y = np.ascontiguousarray(y, np.uint8)
+                xp, yp, is_host = X.ctypes.data, y.ctypes.data, True
+            else:
+                if not (X.is_cuda and y.is_cuda):
+                    raise ValueError("torch inputs must live on the GPU (or pass numpy arrays)")
+                X, y = X.contiguous(), y.contiguous()
+                xp, yp, is_host = X.data_ptr(), y.data_ptr(), False
+            if host is None:
+                host = is_host
+            elif host != is_host:
+                raise ValueError("all datasets of a batch must be on the host, or all on the GPU")
+            self._keep.append((X, y))
+            descs.append((xp, yp, int(X.shape[0]), int(X.shape[1]), xt))
+            shapes.append((int(X.shape[0]), int(X.shape[1])))
+        opt.x_on_host = int(bool(host))
+        if not host:
+            import torch
+            torch.cuda.synchronize()
+        self.record_lambda = record_lambda
+        self.b = hsp_batch_create(descs, counts, opt)
+        self._keep = None  # the library holds its own copies now
+        self.shapes = [shapes[d] for d, c in enumerate(counts) for _ in range(c)]
+        self.chains = [Sampler._borrowed(hsp_batch_chain(self.b, i), N, p, record_lambda, self)
+                       for i, (N, p) in enumerate(self.shapes)]
+
+    def __len__(self):
+        return len(self.chains)
+
+    def chain(self, i):
+        return self.chains[i]
+
+    def sweep(self, n=1):
+        hsp_batch_sweep(self.b, n)
+
+    def sync(self):
+        hsp_batch_sync(self.b)
+
+    def set_timing(self, enable):
+        hsp_batch_set_timing(self.b, enable)
+
+    def timing(self):
+        return hsp_batch_get_timing(self.b)
+
+    def close(self):
+        if self.b:
+            for c in self.chains:
+                c.h = None
+            hsp_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
