@@ -46,6 +46,7 @@ struct hsp_state {
     hipGraphExec_t graph = nullptr;  // one whole sweep (one kernel), recording
     uint64_t* trace = nullptr;        // p-side phase timestamps (diagnostics)
     SweepArgs* dargs = nullptr;       // [0]: a whole sweep, [1]: the last hsp_step
+    const SweepArgs** dtab = nullptr;  // device table {dargs, dargs + 1} for the launches
     const hsp_state* owner = nullptr;  // batch chain: X, y, G, Gp belong to this state
     bool in_batch = false;             // owned by an hsp_batch (not destroyed alone)
     bool timing = false;
@@ -120,7 +121,7 @@ SweepArgs sweep_args(hsp_state* s, uint32_t mode) {
     a.mode = mode;
     a.timeout_ticks = s->timeout_ticks;
     a.trace = dev_ptr(s->trace);
-    a.gp = a.gz = a.zgroups = 0;
+    a.gp = a.gz = a.zgroups = a.block0 = 0;
     return a;
 }
 
@@ -137,7 +138,7 @@ constexpr uint32_t kModeSweep =
 hipError_t enqueue_sweep(hsp_state* s, hipStream_t st) {
     SweepArgs h = sweep_args(s, kModeSweep);
     sweep_finish_args(&h, s->plan);
-    return sweep_launch(h, s->dargs, s->plan, st);
+    return sweep_launch(h, s->dtab, s->plan, st);
 }
 
 hipError_t capture(hsp_state* s, hipGraphExec_t* out) {
@@ -193,7 +194,7 @@ void free_state(hsp_state* s) {
     void* bufs[] = {s->Xbuf, s->y, s->ctrl, s->beta, s->lam, s->nu, s->tau, s->xi, s->b, s->G, s->Gp,
                     s->A, s->Linv, s->Dinv, s->vec, s->partial, s->beta32, s->zdbg, s->adbg,
                     s->ring_beta, s->ring_tau, s->ring_lam, s->trace, s->gpartial,
-                    s->zgrp_count, s->dargs, s->tasks, s->task_off, s->ver};
+                    s->zgrp_count, s->dargs, s->dtab, s->tasks, s->task_off, s->ver};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
@@ -379,6 +380,11 @@ hsp_status chain_impl(hsp_state* s) {
     if (s->opt.record_lambda) HIP_TRY(dalloc(&s->ring_lam, cap * p));
 
     HIP_TRY(dalloc(&s->dargs, 2));
+    HIP_TRY(dalloc(&s->dtab, 2));
+    {
+        const SweepArgs* tab[2] = {s->dargs, s->dargs + 1};
+        HIP_TRY(hipMemcpy(s->dtab, tab, sizeof tab, hipMemcpyHostToDevice));
+    }
     {
         SweepArgs h;
         HIP_TRY(put_args(s, kModeSweep, 0, &h));
@@ -455,8 +461,23 @@ hsp_status hsp_create(const float* X, const uint8_t* y, int64_t N, int64_t p,
 // ---- batches: many chains, one graph launch per sweep ------------------------------
 }  // extern "C"
 
+// Chains that share one launch of the sweep kernel: each has its own p-side
+// group and z-pass blocks, all resident together.
+struct Pack {
+    int xtype = 0;
+    int chunks = 1;  // 16-byte vectors per lane per row: the largest of the pack's chains
+    uint32_t blocks = 0;
+    std::vector<size_t> chains;             // indices into hsp_batch::chains
+    std::vector<uint32_t> gp, gz;           // the pack's blocks per chain
+    SweepArgs* dargs = nullptr;             // one launch description per chain (device)
+    const SweepArgs** dtab = nullptr;       // pointers to them (device)
+    uint16_t* dmap = nullptr;               // block -> chain within the pack (device)
+    std::vector<uint32_t*> sched;           // per-chain task lists and bounds for its gp (device)
+};
+
 struct hsp_batch {
     std::vector<hsp_state*> chains;  // dataset-major; the first chain of each dataset owns its data
+    std::vector<Pack> packs;         // how the chains share launches
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipGraphExec_t graph = nullptr;  // every chain's sweep, one after another
@@ -471,6 +492,13 @@ void free_batch(hsp_batch* b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    for (Pack& pk : b->packs) {
+        if (pk.dargs) (void)hipFree(pk.dargs);
+        if (pk.dtab) (void)hipFree(pk.dtab);
+        if (pk.dmap) (void)hipFree(pk.dmap);
+        for (uint32_t* q : pk.sched)
+            if (q) (void)hipFree(q);
+    }
     for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
     for (auto it = b->chains.rbegin(); it != b->chains.rend(); ++it) free_state(*it);  // borrowers first
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -480,6 +508,152 @@ void free_batch(hsp_batch* b) {
 hsp_status batch_fail(hsp_batch* b, hsp_status code, const std::string& msg) {
     if (b) b->err = msg;
     return code;
+}
+
+// ---- packing chains into shared launches ------------------------------------
+// A cost model of one chain's sweep for a given split of its blocks:
+// the z pass moves its X at a share of the HBM bandwidth proportional to its
+// blocks; the p-side takes the longer of its critical chain and its tile
+// work spread over the group's other blocks (p <= 128: one block).
+struct ChainCost {
+    double bytes;     // X per sweep
+    uint32_t nt;      // 64-wide tiles per side of Q (0: one-block path)
+    uint32_t ntasks;  // tile tasks of the factorisation
+    uint32_t gp_max, gz_max;
+};
+
+double z_time_us(const ChainCost& c, uint32_t gz, double bytes_per_us_per_block) {
+    return c.bytes / (gz * bytes_per_us_per_block) + 5.0;
+}
+
+double p_time_us(const ChainCost& c, uint32_t gp) {
+    if (c.nt == 0) return 60.0;
+    const double chain = 22.0 * c.nt, work = 6.0 * c.ntasks / (gp > 1 ? gp - 1 : 1);
+    return (gp > 1 ? std::max(chain, work) : chain + work) + 30.0;
+}
+
+uint32_t count_tasks(uint32_t nt) {
+    uint32_t n = 0;
+    for (uint32_t k = 0; k < nt; ++k) {
+        const uint32_t m = nt - k - 1;
+        n += 1 + m + k + m * (m + 1) / 2 + m * (k + 1);
+    }
+    return n;
+}
+
+// Split the chains of each storage type into packs that fit the device's
+// resident capacity, and split each pack's blocks among its chains so that
+// the slowest chain of the pack is as fast as the model allows.
+hsp_status plan_packs(hsp_batch* b) {
+    const int num_cus = b->chains[0]->num_cus;
+    for (int xt = 0; xt < 2; ++xt) {
+        std::vector<size_t> ids;
+        int chunks = 1;
+        for (size_t i = 0; i < b->chains.size(); ++i)
+            if (b->chains[i]->x.xtype == xt) {
+                ids.push_back(i);
+                chunks = std::max(chunks, b->chains[i]->plan.chunks);
+            }
+        if (ids.empty()) continue;
+        const int cap = pack_capacity(xt, chunks, num_cus);
+        if (cap < 2) return batch_fail(b, HSP_EHIP, "no resident capacity for a pack");
+        const double bw = 7.0e6 / cap;  // bytes per microsecond per block (about 7 TB/s in all)
+        std::vector<ChainCost> cost(b->chains.size());
+        const int rows = chunks <= 4 ? 8 : (chunks <= 8 ? 4 : 2);
+        for (size_t i : ids) {
+            const hsp_state* s = b->chains[i];
+            ChainCost& c = cost[i];
+            c.bytes = (double)s->x.N * s->x.ld * (xt == 0 ? 4 : 2);
+            c.nt = s->x.p > (uint32_t)kSmallP ? (s->x.p + kTile - 1) / kTile : 0;
+            c.ntasks = c.nt ? count_tasks(c.nt) : 0;
+            c.gp_max = c.nt ? std::min<uint32_t>(kMaxGroup, c.nt * (c.nt + 1) / 2) : 1;
+            const uint32_t tiles = (s->x.N + rows - 1) / rows;
+            c.gz_max = std::max<uint32_t>(1, std::min<uint32_t>(s->plan.gz, (tiles + 3) / 4));
+        }
+        std::sort(ids.begin(), ids.end(), [&](size_t x, size_t y) { return cost[x].bytes > cost[y].bytes; });
+        // packs of at most cap blocks, two blocks per chain at least
+        std::vector<std::vector<size_t>> groups;
+        for (size_t i : ids) {
+            if (groups.empty() || 2 * (groups.back().size() + 1) > (size_t)cap) groups.emplace_back();
+            groups.back().push_back(i);
+        }
+        for (auto& g : groups) {
+            Pack pk;
+            pk.xtype = xt;
+            pk.chunks = chunks;
+            pk.chains = g;
+            pk.gp.assign(g.size(), 1);
+            pk.gz.assign(g.size(), 1);
+            uint32_t used = 2 * (uint32_t)g.size();
+            while (used < (uint32_t)cap) {
+                // the chain predicted to finish last gets one more block where it helps
+                size_t worst = g.size();
+                double tw = -1.0;
+                bool to_z = true;
+                for (size_t j = 0; j < g.size(); ++j) {
+                    const ChainCost& c = cost[g[j]];
+                    const double tz = z_time_us(c, pk.gz[j], bw), tp = p_time_us(c, pk.gp[j]);
+                    const bool can_z = pk.gz[j] < c.gz_max, can_p = pk.gp[j] < c.gp_max;
+                    const bool zj = tz >= tp ? can_z : !can_p;
+                    if (!(zj ? can_z : can_p)) continue;
+                    const double t = std::max(tz, tp);
+                    if (t > tw) {
+                        tw = t;
+                        worst = j;
+                        to_z = zj;
+                    }
+                }
+                if (worst == g.size()) break;
+                if (to_z) ++pk.gz[worst];
+                else ++pk.gp[worst];
+                ++used;
+            }
+            pk.blocks = used;
+            b->packs.push_back(std::move(pk));
+        }
+    }
+    // device descriptions, block maps and schedules
+    for (Pack& pk : b->packs) {
+        const size_t nc = pk.chains.size();
+        if (dalloc(&pk.dargs, nc) || dalloc(&pk.dtab, nc) || dalloc(&pk.dmap, pk.blocks))
+            return batch_fail(b, HSP_ENOMEM, "pack allocation failed");
+        std::vector<SweepArgs> host(nc);
+        std::vector<const SweepArgs*> tab(nc);
+        std::vector<uint16_t> map(pk.blocks);
+        uint32_t blk = 0;
+        for (size_t j = 0; j < nc; ++j) {
+            hsp_state* s = b->chains[pk.chains[j]];
+            SweepArgs h = sweep_args(s, kModeSweep);
+            h.gp = pk.gp[j];
+            h.gz = pk.gz[j];
+            h.zgroups = (h.gz + kZGroup - 1) / kZGroup;
+            h.block0 = blk;
+            if (s->x.p > (uint32_t)kSmallP) {
+                const uint32_t nt = (s->x.p + kTile - 1) / kTile;
+                std::vector<uint32_t> tasks, off;
+                chol_schedule(nt, h.gp, &tasks, &off);
+                uint32_t *dt = nullptr, *doff = nullptr;
+                if (dalloc(&dt, tasks.size()) || dalloc(&doff, off.size()))
+                    return batch_fail(b, HSP_ENOMEM, "pack allocation failed");
+                pk.sched.push_back(dt);
+                pk.sched.push_back(doff);
+                if (hipMemcpy(dt, tasks.data(), tasks.size() * 4, hipMemcpyHostToDevice) ||
+                    hipMemcpy(doff, off.data(), off.size() * 4, hipMemcpyHostToDevice))
+                    return batch_fail(b, HSP_EHIP, "pack schedule upload");
+                h.tasks = dev_ptr(static_cast<const uint32_t*>(dt));
+                h.task_off = dev_ptr(static_cast<const uint32_t*>(doff));
+            }
+            host[j] = h;
+            tab[j] = pk.dargs + j;
+            for (uint32_t q = 0; q < h.gp + h.gz; ++q) map[blk + q] = (uint16_t)j;
+            blk += h.gp + h.gz;
+        }
+        if (hipMemcpy(pk.dargs, host.data(), nc * sizeof(SweepArgs), hipMemcpyHostToDevice) ||
+            hipMemcpy(pk.dtab, tab.data(), nc * sizeof(const SweepArgs*), hipMemcpyHostToDevice) ||
+            hipMemcpy(pk.dmap, map.data(), map.size() * 2, hipMemcpyHostToDevice))
+            return batch_fail(b, HSP_EHIP, "pack upload");
+    }
+    return HSP_OK;
 }
 
 }  // namespace
@@ -569,9 +743,16 @@ hsp_status hsp_batch_sweep(hsp_batch* b, int64_t n) {
             return batch_fail(b, HSP_EINVAL, "the sweep counter would exceed 2^32");
     }
     if (!b->graph) {
+        if (b->packs.empty()) {
+            hsp_status st = plan_packs(b);
+            if (st != HSP_OK) return st;
+        }
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-        for (size_t i = 0; !e && i < b->chains.size(); ++i) e = enqueue_sweep(b->chains[i], b->stream);
+        for (size_t i = 0; !e && i < b->packs.size(); ++i) {
+            const Pack& pk = b->packs[i];
+            e = pack_launch(pk.xtype, pk.chunks, pk.dtab, pk.dmap, pk.blocks, b->stream);
+        }
         hipError_t e2 = hipStreamEndCapture(b->stream, &g);
         if (!e) e = e2;
         if (!e) e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
@@ -763,7 +944,7 @@ hsp_status hsp_step(hsp_state* s, uint32_t which) {
     SweepArgs h;
     HIP_TRY(hipStreamSynchronize(s->stream));
     HIP_TRY(put_args(s, mode, 1, &h));
-    HIP_TRY(sweep_launch(h, s->dargs + 1, s->plan, s->stream));
+    HIP_TRY(sweep_launch(h, s->dtab + 1, s->plan, s->stream));
     hsp_status st = sync_state(s);
     if (st) return st;
     if (which & HSP_STEP_ADVANCE) {

@@ -119,6 +119,7 @@ struct SweepArgs {
     uint32_t gp;             // blocks of the p-side group (first in the grid)
     uint32_t gz;             // z-pass blocks (after the group)
     uint32_t zgroups;        // ceil(gz / kZGroup)
+    uint32_t block0;         // first grid block of this chain (several chains share a pack launch)
     uint64_t timeout_ticks;  // bound of every wait, in s_memrealtime ticks
     HSP_GLOBAL uint64_t* trace;         // optional: kTraceSlots timestamps per group block
     HSP_GLOBAL const uint32_t* tasks;   // tile path: every group block's task list, concatenated
@@ -163,9 +164,16 @@ struct SweepPlan {
 hipError_t sweep_plan(const XLayout& x, int num_cus, SweepPlan* plan);
 // Fill gp, gz and zgroups of a launch description from the plan and its mode.
 void sweep_finish_args(SweepArgs* a, const SweepPlan& plan);
-// Enqueue one launch of the sweep kernel; dev is a device copy of host.
-hipError_t sweep_launch(const SweepArgs& host, const SweepArgs* dev, const SweepPlan& plan,
+// Enqueue one launch of the sweep kernel for one chain: table is a device
+// array whose entry 0 points to a device copy of host.
+hipError_t sweep_launch(const SweepArgs& host, const SweepArgs* const* table, const SweepPlan& plan,
                         hipStream_t st);
+// Several chains in one launch (a pack): block b runs chain chain_of_block[b]
+// (device arrays); every chain's description has its block0, gp and gz set.
+// pack_capacity: resident blocks of that kernel on the device.
+int pack_capacity(int xtype, int chunks, int num_cus);
+hipError_t pack_launch(int xtype, int chunks, const SweepArgs* const* table, const uint16_t* chain_of_block,
+                       uint32_t blocks, hipStream_t st);
 
 // G = X^T X (p x p float64, leading dimension p); work must hold
 // gram_work_doubles(x) doubles.

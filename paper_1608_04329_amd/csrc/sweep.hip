@@ -23,18 +23,24 @@ namespace {
 // The launch's description lives in device memory (read through the scalar
 // cache as needed) rather than in kernel arguments, which would otherwise stay
 // pinned in scalar registers for the whole kernel.
+// A launch may serve several independent chains (a batch): block b belongs
+// to chain chain_of_block[b] (chain 0 for all when the map is null) and runs
+// that chain's role at position b - block0 of its blocks.
 template <int XT, int KC, int R>
-__global__ __launch_bounds__(kThreads, 2) void sweep_kernel(const SweepArgs* __restrict__ args) {
+__global__ __launch_bounds__(kThreads, 2) void sweep_kernel(const SweepArgs* const* __restrict__ args,
+                                                            const uint16_t* __restrict__ chain_of_block) {
     __shared__ double lds[kLdsDoubles];
-    const SweepArgs& a = *args;
+    const uint32_t c = chain_of_block ? chain_of_block[blockIdx.x] : 0u;
+    const SweepArgs& a = *args[c];
+    const uint32_t b = blockIdx.x - a.block0;
     const uint32_t k = a.ctrl->sweep + 1u;
-    if (blockIdx.x < a.gp) pside_role(a, blockIdx.x, k, lds);
-    else zpass_role<XT, KC, R>(a, blockIdx.x - a.gp, a.gz, k, lds);
+    if (b < a.gp) pside_role(a, b, k, lds);
+    else zpass_role<XT, KC, R>(a, b - a.gp, a.gz, k, lds);
 }
 
 constexpr int rows_for_chunks(int kc) { return kc <= 4 ? 8 : (kc <= 8 ? 4 : 2); }
 
-using KernelFn = void (*)(const SweepArgs*);
+using KernelFn = void (*)(const SweepArgs* const*, const uint16_t*);
 
 template <int XT, int... KCs>
 KernelFn pick(int kc, std::integer_sequence<int, KCs...>) {
@@ -82,13 +88,31 @@ void sweep_finish_args(SweepArgs* a, const SweepPlan& plan) {
     a->zgroups = (a->gz + kZGroup - 1) / kZGroup;
 }
 
-hipError_t sweep_launch(const SweepArgs& host, const SweepArgs* dev, const SweepPlan& plan,
+hipError_t sweep_launch(const SweepArgs& host, const SweepArgs* const* table, const SweepPlan& plan,
                         hipStream_t st) {
     KernelFn f = kernel_for(host.x.xtype, plan.chunks);
     if (!f) return hipErrorInvalidValue;
-    void* args[] = {&dev};
+    const uint16_t* none = nullptr;
+    void* args[] = {&table, &none};
     return hipLaunchKernel(reinterpret_cast<const void*>(f), dim3(host.gp + host.gz), dim3(kThreads),
                            args, 0, st);
+}
+
+int pack_capacity(int xtype, int chunks, int num_cus) {
+    KernelFn f = kernel_for(xtype, chunks);
+    int per_cu = 0;
+    if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(f),
+                                                           kThreads, 0) != hipSuccess)
+        return 0;
+    return per_cu * num_cus;
+}
+
+hipError_t pack_launch(int xtype, int chunks, const SweepArgs* const* table, const uint16_t* chain_of_block,
+                       uint32_t blocks, hipStream_t st) {
+    KernelFn f = kernel_for(xtype, chunks);
+    if (!f) return hipErrorInvalidValue;
+    void* args[] = {&table, &chain_of_block};
+    return hipLaunchKernel(reinterpret_cast<const void*>(f), dim3(blocks), dim3(kThreads), args, 0, st);
 }
 
 }  // namespace hsp

@@ -400,15 +400,18 @@ class Batch:
 
     datasets: list of (X, y) or (X, y, x_type) with X, y as for Sampler (all on
     the GPU, or all numpy); chains: chains per dataset (an int for all).
-    Chain i (dataset-major) uses chain id chain_id + i.
+    Chain i (dataset-major) uses chain id chain_id + i.  The chains share
+    launches of the sweep kernel (each with its own blocks), so a chain's
+    rounding of X^T z can differ from the same chain run alone.
     """
 
     def __init__(self, datasets, chains=1, seed=1, chain_id=0, record_lambda=False, thin=1,
-                 max_draws=1024, stream=None):
+                 max_draws=1024, debug_store_z=False, stream=None):
         load()
         opt = hsp_default_options()
         opt.seed = seed
         opt.chain_id = chain_id
+        opt.debug_store_z = int(debug_store_z)
         opt.record_lambda = int(record_lambda)
         opt.thin = thin
         opt.max_draws = max_draws
