@@ -17,6 +17,16 @@ namespace hsp {
 #define HSP_GLOBAL
 #endif
 
+// The launch description itself is read-only for a whole launch: device code
+// reaches it through the constant address space, which lets the compiler keep,
+// hoist and re-load its fields freely (as it does for kernel arguments) across
+// the kernel's atomics and fences.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define HSP_CONST __attribute__((address_space(4)))
+#else
+#define HSP_CONST
+#endif
+
 // Host side: a device pointer as stored in a launch description.
 template <class T>
 inline HSP_GLOBAL T* dev_ptr(T* p) {
@@ -28,7 +38,7 @@ constexpr int kMaxP = 4096;            // largest p the register-tiled z pass su
 constexpr uint32_t kMaxRounds = 2048;  // 4096 truncated-normal proposals per row
 constexpr int kThreads = 256;          // threads per block of the sweep kernel
 constexpr int kTile = 64;              // p-side tile edge
-constexpr int kSmallP = 128;           // p up to this runs the one-block p-side path
+constexpr int kSmallP = 16;            // p up to this runs the one-block p-side path
 #ifndef HSP_MAX_GROUP
 #define HSP_MAX_GROUP 32
 #endif
@@ -126,6 +136,9 @@ struct SweepArgs {
     HSP_GLOBAL const uint32_t* task_off;  // gp + 1 offsets into tasks
     HSP_GLOBAL uint32_t* ver;           // tile path: 2 x nt x nt tile version counters (zero between launches)
 };
+
+// Device view of a launch description.
+using Args = const HSP_CONST SweepArgs;
 
 // Diagnostic trace per group block: slot 0 = start, slots 1.. one value per
 // event in order (group barriers: a timestamp; per factorisation task: its

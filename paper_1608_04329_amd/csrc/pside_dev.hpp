@@ -184,7 +184,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return s;
 }
 
-__device__ __forceinline__ uint32_t record_slot(const SweepArgs& a, uint32_t k, bool* keep) {
+__device__ __forceinline__ uint32_t record_slot(Args& a, uint32_t k, bool* keep) {
     const uint32_t since = k - a.ctrl->draw_base;
     *keep = (a.mode & kModeRecord) && since % a.thin == 0;
     return *keep ? (since / a.thin - 1u) % a.capacity : 0u;
@@ -192,7 +192,7 @@ __device__ __forceinline__ uint32_t record_slot(const SweepArgs& a, uint32_t k, 
 
 // ---- lambda^-2 and tau^-2 (every block of the group computes them) ---------------
 // Returns tau^-2 (new if kModeTau).  Block `writer` stores lambda^-2 and tau^-2.
-__device__ double hyper_lambda_tau(const SweepArgs& a, uint32_t k, bool writer, double* red) {
+__device__ double hyper_lambda_tau(Args& a, uint32_t k, bool writer, double* red) {
     const uint32_t p = a.x.p;
     const double tau_old = *a.tau_m2;
     double acc = 0.0;
@@ -266,7 +266,7 @@ __device__ double hyper_lambda_tau(const SweepArgs& a, uint32_t k, bool writer, 
 }
 
 // tau^-2 of this sweep: the scratch slot if it was drawn in this launch.
-__device__ __forceinline__ double current_tau(const SweepArgs& a) {
+__device__ __forceinline__ double current_tau(Args& a) {
     // written by block 0 of the group in this launch: read past the scalar cache
     return (a.mode & kModeTau)
                ? __hip_atomic_load(a.vec + 2 * a.x.p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
@@ -274,7 +274,7 @@ __device__ __forceinline__ double current_tau(const SweepArgs& a) {
 }
 
 // nu^-1 and xi^-1 from the (new) lambda^-2 and tau^-2 in memory.
-__device__ void hyper_nu_xi(const SweepArgs& a, uint32_t k) {
+__device__ void hyper_nu_xi(Args& a, uint32_t k) {
     const uint32_t p = a.x.p;
     for (uint32_t j = threadIdx.x; j < p; j += kThreads) {
         const Words4 w = draw_words(a.seed, j, k, kTagNu, 0, a.chain);
@@ -326,7 +326,7 @@ __device__ void wave_solve(const double* U, uint32_t p, double (&r)[2], bool for
     }
 }
 
-__device__ void small_path(const SweepArgs& a, Group& g, uint32_t k, double* lds) {
+__device__ void small_path(Args& a, Group& g, uint32_t k, double* lds) {
     const uint32_t p = a.x.p;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     double tau = hyper_lambda_tau(a, k, true, lds);
@@ -693,7 +693,7 @@ __device__ bool factor_diag(Tile& S, Tile& T, uint64_t* rec) {
 // Factor diagonal block kb held in S (its upper part; the rest is not read):
 // store U_kk into A, D = U_kk^-1 into Dinv[kb] and D^T = L^-1_kk into Linv.
 // Reports a failed pivot.  On return S = U_kk and T = D^T.
-__device__ void diag_factor(const SweepArgs& a, uint32_t kb, Tile& S, Tile& T, uint64_t* rec) {
+__device__ void diag_factor(Args& a, uint32_t kb, Tile& S, Tile& T, uint64_t* rec) {
     const uint32_t P = padded(a.x.p), k0 = kb * kTile;
     stamp_at(rec, 0);
     if (factor_diag(S, T, rec)) {
@@ -719,7 +719,7 @@ __device__ void diag_factor(const SweepArgs& a, uint32_t kb, Tile& S, Tile& T, u
 // (i, j), j <= i, v of its i - j updates (plus 1 once final).  Each task waits
 // for the versions it reads, then publishes the version it wrote.  Returns
 // false if the group is failing.
-__device__ bool run_tasks(const SweepArgs& a, Group& g, uint32_t rank, double tau, Tile& S, Tile& T,
+__device__ bool run_tasks(Args& a, Group& g, uint32_t rank, double tau, Tile& S, Tile& T,
                           double* flag) {
     const uint32_t p = a.x.p, P = padded(p), nt = P / kTile;
     uint32_t* vU = a.ver;
@@ -874,7 +874,7 @@ __device__ bool run_tasks(const SweepArgs& a, Group& g, uint32_t rank, double ta
     return true;
 }
 
-__device__ void tile_path(const SweepArgs& a, Group& g, uint32_t rank, uint32_t k, double* lds) {
+__device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* lds) {
     const uint32_t p = a.x.p, P = padded(p);
     Tile& S = *reinterpret_cast<Tile*>(lds);
     Tile& T = *reinterpret_cast<Tile*>(lds + kTile * kTileLd);
@@ -1025,7 +1025,7 @@ __device__ void tile_path(const SweepArgs& a, Group& g, uint32_t rank, uint32_t 
 }
 
 // The whole p-side role of block `rank` of the group.
-__device__ __forceinline__ void pside_role(const SweepArgs& a, uint32_t rank, uint32_t k, double* lds) {
+__device__ __forceinline__ void pside_role(Args& a, uint32_t rank, uint32_t k, double* lds) {
     // The group's waves share SIMDs with z-pass waves; their latency-bound
     // chain gets the higher issue priority.
     __builtin_amdgcn_s_setprio(3);

@@ -12,6 +12,7 @@
 // The group blocks come first in the grid: they are dispatched before any
 // z-pass block and stay resident, so their barriers only ever wait on
 // blocks that are running.  The z-pass blocks never wait on anything.
+#include <algorithm>
 #include <utility>
 
 #include "pside_dev.hpp"
@@ -27,15 +28,19 @@ namespace {
 // to chain chain_of_block[b] (chain 0 for all when the map is null) and runs
 // that chain's role at position b - block0 of its blocks.
 template <int XT, int KC, int R>
-__global__ __launch_bounds__(kThreads, 2) void sweep_kernel(const SweepArgs* const* __restrict__ args,
-                                                            const uint16_t* __restrict__ chain_of_block) {
-    __shared__ double lds[kLdsDoubles];
-    const uint32_t c = chain_of_block ? chain_of_block[blockIdx.x] : 0u;
-    const SweepArgs& a = *args[c];
+__device__ __forceinline__ void run_block(Args& a, double* lds) {
     const uint32_t b = blockIdx.x - a.block0;
     const uint32_t k = a.ctrl->sweep + 1u;
     if (b < a.gp) pside_role(a, b, k, lds);
     else zpass_role<XT, KC, R>(a, b - a.gp, a.gz, k, lds);
+}
+
+template <int XT, int KC, int R>
+__global__ __launch_bounds__(kThreads, 2) void sweep_kernel(const SweepArgs* const* __restrict__ args,
+                                                            const uint16_t* __restrict__ chain_of_block) {
+    __shared__ double lds[kLdsDoubles];
+    const uint32_t c = chain_of_block ? chain_of_block[blockIdx.x] : 0u;
+    run_block<XT, KC, R>(*(Args*)args[c], lds);
 }
 
 constexpr int rows_for_chunks(int kc) { return kc <= 4 ? 8 : (kc <= 8 ? 4 : 2); }

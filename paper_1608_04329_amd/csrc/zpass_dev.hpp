@@ -78,7 +78,7 @@ __device__ __forceinline__ void tn_candidate(float mu, bool gauss, float theta, 
 
 // The z-pass role of the sweep kernel: block zrank of nz z-pass blocks.
 template <int XT, int KC, int R>
-__device__ __forceinline__ void zpass_role(const SweepArgs& a, uint32_t zrank, uint32_t nz,
+__device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
                                            uint32_t ksweep, double* red) {
     if (zrank >= nz) return;  // no z-pass work in this launch
     constexpr int VEC = XTraits<XT>::VEC;
