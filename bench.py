@@ -53,14 +53,20 @@ def parse():
 
 
 def kernel_fingerprint():
-    """Hash of the HIP sources: stored counter readings apply only to the same kernels."""
+    """Hash of the library's sources with comments and layout removed: stored
+    counter readings apply only to the same code, whatever its comments say."""
     import hashlib
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1608_04329_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".hip", ".hpp", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+            with open(os.path.join(csrc, name), encoding="utf-8") as f:
+                text = f.read()
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", " ", text)
+            text = " ".join(text.split())
+            h.update(name.encode() + b"\0" + text.encode())
     return h.hexdigest()[:16]
 
 
@@ -152,8 +158,8 @@ def run_batch(a):
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the row-sharded design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (several GPUs "
+              "would each sweep a row shard of X and sum X^T z across them).", file=sys.stderr)
         sys.exit(2)
     if a.batch:
         run_batch(a)

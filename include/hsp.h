@@ -220,7 +220,7 @@ hsp_status hsp_get_timing(hsp_state* s, double* zpass_ms, double* sweep_ms, int6
 /* Diagnostics: when enabled, every launch of the sweep kernel stores, per
  * block of its p-side group, a timestamp at the start (slot 0); then, in
  * order from slot 1 up to slot 447, one value per event: a timestamp for each
- * group barrier passed, and for each factorisation task (p > 128) its index + 1
+ * group barrier passed, and for each factorisation task (p > 16) its index + 1
  * in the task lists of hsp_tile_schedule plus one, then timestamps of when its
  * inputs were ready, its input tiles were loaded and it was done; from slot
  * 448, five records of 12 slots for the diagonal tiles the block factored
@@ -233,7 +233,7 @@ hsp_status hsp_set_phase_trace(hsp_state* s, int32_t enable);
 hsp_status hsp_get_phase_trace(hsp_state* s, uint64_t* out, int64_t* group_blocks, int64_t* slots,
                                double* ticks_per_us);
 
-/* The factorisation schedule for p > 128 (host only, no device work): the
+/* The factorisation schedule for p > 16 (host only, no device work): the
  * Cholesky factorisation of Q by 64 x 64 tiles (Section 5, beta step iii),
  * with the same row operations applied to an identity block, is split into
  * tile tasks that the p-side blocks of the sweep kernel run.  nt =

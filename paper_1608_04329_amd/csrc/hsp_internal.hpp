@@ -151,7 +151,7 @@ constexpr int kTraceSeq = 448;
 constexpr int kTraceRec = 12;
 constexpr int kTraceRecs = 5;
 
-// ---- tasks of the tiled factorisation (p > 128) ----------------------------------
+// ---- tasks of the tiled factorisation (p > 16) ----------------------------------
 enum : uint32_t { kTaskPotrf = 0u, kTaskTrsm = 1u, kTaskGemm = 2u, kTaskPanel = 3u };
 // type (2 bits) | part (0: U, 1: L^-1) | step k | tile row i | tile column j (7 bits each)
 __host__ __device__ constexpr uint32_t task_code(uint32_t type, uint32_t part, uint32_t k, uint32_t i,

@@ -11,11 +11,11 @@
 // Cholesky factorisation of Q depend only on the previous sweep, so the group
 // runs them while the z pass streams X; beta waits for the z pass.
 //
-// beta for p <= 128 (one block): Q packed in LDS, Q = U^T U by a right-looking
+// beta for p <= 16 (one block): Q packed in LDS, Q = U^T U by a right-looking
 // Cholesky, then s ~ N(0, I), U v = s, U^T w = b, U mu = w, beta = mu + v
 // (Section 5, beta steps ii-viii).
 //
-// beta for p > 128 (gp blocks, 64 x 64 tiles): a right-looking blocked
+// beta for p > 16 (gp blocks, 64 x 64 tiles): a right-looking blocked
 // Cholesky that applies the same row operations to an identity block, so it
 // produces U and L^-1 = U^-T together (the factorisation of [Q | I]).  Then
 //   y = L^-1 b + s,   beta = L^-T y = U^-1 U^-T b + U^-1 s,
@@ -286,7 +286,7 @@ __device__ void hyper_nu_xi(Args& a, uint32_t k) {
     }
 }
 
-// ---- one-block path, p <= 128 ----------------------------------------------------
+// ---- one-block path, p <= 16 -----------------------------------------------------
 __device__ __forceinline__ uint32_t pk(uint32_t p, uint32_t i, uint32_t j) {
     // packed upper triangle, row-major: row i starts at i p - i (i - 1) / 2
     return i * p - (i * (i - 1u)) / 2u + (j - i);
@@ -428,7 +428,7 @@ __device__ void small_path(Args& a, Group& g, uint32_t k, double* lds) {
     }
 }
 
-// ---- tile path, p > 128 ----------------------------------------------------------
+// ---- tile path, p > 16 ----------------------------------------------------------
 // The tile path works on P x P matrices, P = p rounded up to a multiple of 64,
 // leading dimension P: Gp holds G with an identity block on the padding, so
 // the factor, L^-1 and Q^-1 carry an identity block there too and no tile

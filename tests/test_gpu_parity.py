@@ -18,7 +18,10 @@ from gpu_util import b_scale, dataset, need_gpu, random_state, z_scale
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(5003, 2), (5003, 10), (4099, 100), (3001, 130), (2051, 257), (2003, 1000)]
+# p = 16 is the largest p of the one-block p-side path, p = 17 the smallest of
+# the tiled one (a single 64-wide tile).
+SHAPES = [(5003, 2), (5003, 10), (4001, 16), (4001, 17), (4099, 100), (3001, 130), (2051, 257),
+          (2003, 1000)]
 
 
 @pytest.fixture(scope="module")
@@ -133,7 +136,7 @@ def test_beta_step(env, orc, N, p):
     s.close()
 
 
-@pytest.mark.parametrize("N,p", [(5003, 10), (4099, 100), (2051, 257)])
+@pytest.mark.parametrize("N,p", [(5003, 10), (4001, 17), (4099, 100), (2051, 257)])
 def test_sweep_trajectory(env, orc, N, p):
     """Five whole sweeps from the cold start, state compared after each."""
     torch, hsp = env

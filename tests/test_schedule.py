@@ -1,4 +1,4 @@
-"""Host logic: the static task schedule of the tiled factorisation (p > 128).
+"""Host logic: the static task schedule of the tiled factorisation (p > 16).
 
 The factorisation of [Q | I] by 64 x 64 tiles (Section 5, beta step iii, with
 L^-1 = U^-T carried along) runs as tile tasks from per-block lists.  These
