@@ -29,7 +29,7 @@ struct hsp_state {
     uint8_t* y = nullptr;
     Ctrl* ctrl = nullptr;
     double *beta = nullptr, *lam = nullptr, *nu = nullptr, *tau = nullptr, *xi = nullptr;
-    double *b = nullptr, *G = nullptr, *Gp = nullptr, *A = nullptr, *Linv = nullptr, *Dinv = nullptr;
+    double *b = nullptr, *G = nullptr, *Gp = nullptr, *A = nullptr, *Linv = nullptr;
     double *vec = nullptr, *partial = nullptr, *gpartial = nullptr;
     uint32_t* zgrp_count = nullptr;
     uint32_t *tasks = nullptr, *task_off = nullptr, *ver = nullptr;  // tile path schedule
@@ -105,7 +105,6 @@ SweepArgs sweep_args(hsp_state* s, uint32_t mode) {
     a.Gp = dev_ptr(s->Gp);
     a.A = dev_ptr(s->A);
     a.Linv = dev_ptr(s->Linv);
-    a.Dinv = dev_ptr(s->Dinv);
     a.tasks = dev_ptr(s->tasks);
     a.task_off = dev_ptr(s->task_off);
     a.ver = dev_ptr(s->ver);
@@ -192,7 +191,7 @@ void free_state(hsp_state* s) {
         s->Gp = nullptr;
     }
     void* bufs[] = {s->Xbuf, s->y, s->ctrl, s->beta, s->lam, s->nu, s->tau, s->xi, s->b, s->G, s->Gp,
-                    s->A, s->Linv, s->Dinv, s->vec, s->partial, s->beta32, s->zdbg, s->adbg,
+                    s->A, s->Linv, s->vec, s->partial, s->beta32, s->zdbg, s->adbg,
                     s->ring_beta, s->ring_tau, s->ring_lam, s->trace, s->gpartial,
                     s->zgrp_count, s->dargs, s->dtab, s->tasks, s->task_off, s->ver};
     for (void* p : bufs)
@@ -341,7 +340,6 @@ hsp_status chain_impl(hsp_state* s) {
     if (p > kSmallP) {
         HIP_TRY(dalloc(&s->A, P * P));
         HIP_TRY(dalloc(&s->Linv, P * P));
-        HIP_TRY(dalloc(&s->Dinv, P * kTile));
         HIP_TRY(hipMemsetAsync(s->A, 0, P * P * sizeof(double), s->stream));
         HIP_TRY(hipMemsetAsync(s->Linv, 0, P * P * sizeof(double), s->stream));
     }

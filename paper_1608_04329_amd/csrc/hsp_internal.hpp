@@ -115,7 +115,6 @@ struct SweepArgs {
     HSP_GLOBAL const double* Gp;   // tile path: P x P, G with an identity block on the padding
     HSP_GLOBAL double* A;          // tile path, P x P: U (P = p rounded up to 64)
     HSP_GLOBAL double* Linv;       // tile path, P x P: lower triangle holds L^-1 = U^-T
-    HSP_GLOBAL double* Dinv;       // ceil(p/64) x 64 x 64: inverses of U's diagonal blocks
     HSP_GLOBAL double* vec;        // 2 p scratch
     HSP_GLOBAL double* ring_beta;  // capacity x p
     HSP_GLOBAL double* ring_tau;   // capacity

@@ -30,6 +30,7 @@
 
 #include "hsp_internal.hpp"
 #include "philox.hpp"
+#include "sync_dev.hpp"
 
 namespace hsp {
 
@@ -82,12 +83,6 @@ __device__ __forceinline__ void wait_count(unsigned long long* ctr, unsigned lon
         backoff(nap, cap);
     }
 }
-
-// Cross-block ordering, one fence per block: before publishing, every wave
-// waits for its own stores and one thread writes the cache back (release);
-// after observing, one thread invalidates (acquire) before the block reads.
-__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 // Tiles that the factorisation's tasks hand to each other move through
 // device-coherent loads and stores (they bypass the non-coherent caches), so
@@ -326,6 +321,11 @@ __device__ void wave_solve(const double* U, uint32_t p, double (&r)[2], bool for
     }
 }
 
+// LDS offset (doubles) of b on the one-block path, past the packed factor.
+constexpr uint32_t kSmallBOff = 512;
+static_assert(kSmallP * (kSmallP + 1) / 2 <= (int)kSmallBOff && kSmallBOff + kSmallP <= (uint32_t)kLdsDoubles,
+              "one-block path LDS layout");
+
 __device__ void small_path(Args& a, Group& g, uint32_t k, double* lds) {
     const uint32_t p = a.x.p;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -377,13 +377,14 @@ __device__ void small_path(Args& a, Group& g, uint32_t k, double* lds) {
             fence_acquire();
         }
         __syncthreads();
-        // one column per thread, summed over the group partial rows in order
+        // one column per thread, summed over the group partial rows in order;
+        // wave 0 takes b from LDS below
         for (uint32_t j = threadIdx.x; j < p; j += kThreads) {
             double s = 0.0;
             for (uint32_t r = 0; r < a.zgroups; ++r) s += a.gpartial[(size_t)r * a.x.ld + j];
             a.b[j] = s;
+            lds[kSmallBOff + j] = s;
         }
-        __threadfence();
         __syncthreads();
     }
     bool keep;
@@ -400,7 +401,7 @@ __device__ void small_path(Args& a, Group& g, uint32_t k, double* lds) {
             if (j < p) {
                 const Words4 wd = draw_words(a.seed, j, k, kTagBetaS, 0, a.chain);
                 v[q] = box_muller_d(u01d(wd.w0), u01d(wd.w1));
-                w[q] = a.b[j];
+                w[q] = (a.mode & kModeZ) ? lds[kSmallBOff + j] : a.b[j];
             }
         }
         wave_solve(U, p, v, false);  // U v = s
@@ -601,10 +602,13 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 // (lower), i.e. the factorisation of [S | I] by row operations.
 //
 // Four row panels of 16.  For each, wave 0 eliminates the panel in registers,
-// columns across the lanes: at step c the pivot is lane (r0 + c)'s entry c,
-// row c is scaled by 1/sqrt(pivot) and every later panel row i loses U[c][i]
-// times it (U[c][i] read from lane r0 + i), in the S part and in the identity
-// part alike.  That factors the panel's diagonal block and solves its other
+// columns across the lanes.  At step c the pivot d is lane (r0 + c)'s entry of
+// row c and every later panel row i loses m_i / d times row c, m_i being row
+// c's entry in lane r0 + i, in the S part and in the identity part alike; row
+// c is then scaled by 1/sqrt(d).  The multipliers are read from row c before
+// it is scaled, so those reads do not wait for the square root, and row c + 1
+// is updated first, so the next pivot's chain overlaps the other rows'
+// updates.  That factors the panel's diagonal block and solves its other
 // columns at once.  Then all four waves subtract the panel's rank-16
 // contribution from the rows below on the matrix cores, as 16 x 16 blocks:
 // S(I, J) -= U(P, I)^T U(P, J) for P < I <= J, and T(I, J) -= U(P, I)^T T(P, J)
@@ -615,7 +619,6 @@ __device__ bool factor_diag(Tile& S, Tile& T, uint64_t* rec) {
     double* flag = &T[kTile - 1][kTile];  // padding corner, not part of the tile
     for (int e = threadIdx.x; e < kTile * kTile; e += kThreads) T[e / kTile][e % kTile] = e / kTile == e % kTile ? 1.0 : 0.0;
     __syncthreads();
-#pragma unroll
     for (int P = 0; P < 4; ++P) {
         const int r0 = 16 * P;
         if (wave == 0) {
@@ -626,19 +629,30 @@ __device__ bool factor_diag(Tile& S, Tile& T, uint64_t* rec) {
                 w[c] = T[r0 + c][lane];
             }
             bool ok = true;
+            double d = rdlane(a[0], r0);
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
-                const double d = rdlane(a[c], r0 + c);
+                double m[16];
+#pragma unroll
+                for (int i = c + 1; i < 16; ++i) m[i] = rdlane(a[c], r0 + i);
                 ok = ok && (d > 0.0);
                 const double rs = rsqrt_nr(d);
+                const double inv = rs * rs;
+                const double ta = a[c] * inv, tw = w[c] * inv;
+                double dn = 0.0;
+                if (c + 1 < 16) {
+                    a[c + 1] = fma(-m[c + 1], ta, a[c + 1]);
+                    w[c + 1] = fma(-m[c + 1], tw, w[c + 1]);
+                    dn = rdlane(a[c + 1], r0 + c + 1);
+                }
+#pragma unroll
+                for (int i = c + 2; i < 16; ++i) {
+                    a[i] = fma(-m[i], ta, a[i]);
+                    w[i] = fma(-m[i], tw, w[i]);
+                }
                 a[c] = lane == r0 + c ? d * rs : a[c] * rs;
                 w[c] *= rs;
-#pragma unroll
-                for (int i = c + 1; i < 16; ++i) {
-                    const double m = rdlane(a[c], r0 + i);
-                    a[i] = fma(-m, a[c], a[i]);
-                    w[i] = fma(-m, w[c], w[i]);
-                }
+                d = dn;
             }
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
@@ -690,20 +704,18 @@ __device__ bool factor_diag(Tile& S, Tile& T, uint64_t* rec) {
     return true;
 }
 
-// Factor diagonal block kb held in S (its upper part; the rest is not read):
-// store U_kk into A, D = U_kk^-1 into Dinv[kb] and D^T = L^-1_kk into Linv.
-// Reports a failed pivot.  On return S = U_kk and T = D^T.
+// Factor diagonal block kb held in S (its upper part; the rest is not read)
+// and store L^-1_kk = U_kk^-T into Linv: the triangular solves read it from
+// there (U_kk itself is needed by nothing after this block).  Reports a
+// failed pivot.  On return S = U_kk and T = U_kk^-T.
 __device__ void diag_factor(Args& a, uint32_t kb, Tile& S, Tile& T, uint64_t* rec) {
     const uint32_t P = padded(a.x.p), k0 = kb * kTile;
     stamp_at(rec, 0);
     if (factor_diag(S, T, rec)) {
-        double* D = a.Dinv + (size_t)kb * kTile * kTile;
         const int c = threadIdx.x & (kTile - 1), rb = threadIdx.x >> 6;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int r = rb + 4 * q;
-            stc(a.A + (size_t)(k0 + r) * P + k0 + c, S[r][c]);
-            stc(D + r * kTile + c, T[c][r]);
             stc(a.Linv + (size_t)(k0 + r) * P + k0 + c, T[r][c]);
         }
     } else if (threadIdx.x == 0) {
@@ -822,26 +834,13 @@ __device__ bool run_tasks(Args& a, Group& g, uint32_t rank, double tau, Tile& S,
             val = kb + 1;
             out2 = &vL[kb * nt + kb];
         } else if (type == kTaskTrsm) {
-            // row kb times D = U_kk^-1: X_kj = D^T X_kj
-            const double* Dk = a.Dinv + (size_t)kb * kTile * kTile;
+            // row kb times U_kk^-1: X_kj = L^-1_kk X_kj, L^-1_kk from Linv
             const uint32_t j0 = jb * kTile;
-            const int c = threadIdx.x & (kTile - 1), rb = threadIdx.x >> 6;
-            const double* src = (part == 0 ? (kb == 0 ? a.Gp : a.A) : a.Linv) + (size_t)(k0 + rb) * P + j0 + c;
-            double v[16], x[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                v[q] = ldc(Dk + (rb + 4 * q) * kTile + c);
-                x[q] = ldc(src + (size_t)(4 * q) * P);
-            }
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                S[rb + 4 * q][c] = v[q];
-                T[rb + 4 * q][c] = x[q];
-            }
+            load_tiles(S, a.Linv, k0, k0, T, part == 0 ? (kb == 0 ? a.Gp : a.A) : a.Linv, k0, j0, P);
             __syncthreads();
             stamp(g);
             MAcc acc;
-            gemm_tn(S, T, acc);
+            gemm_tn<true>(S, T, acc);
             MTile zero;
             load_tile_m(zero, nullptr, P, 0, 0, false, 0.0, nullptr, p);
             put_tile_m(part == 0 ? a.A : a.Linv, P, k0, j0, acc, 1.0, zero);

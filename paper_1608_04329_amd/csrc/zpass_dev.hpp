@@ -26,6 +26,7 @@
 #pragma once
 #include "hsp_internal.hpp"
 #include "philox.hpp"
+#include "sync_dev.hpp"
 
 namespace hsp {
 
@@ -247,10 +248,10 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
     const uint32_t g0 = grp * kZGroup;
     const uint32_t gsize = min((uint32_t)kZGroup, nz - g0);
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        fence_release();
         const uint32_t old = atomicAdd(&a.zgrp_count[grp], 1u);
         const bool lst = old == gsize - 1;
-        if (lst) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (lst) fence_acquire();
         red[0] = lst ? 1.0 : 0.0;
     }
     __syncthreads();
@@ -271,7 +272,7 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
         __syncthreads();
         if (threadIdx.x == 0) {
             a.zgrp_count[grp] = 0u;  // every block of the group has arrived
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            fence_release();
             atomicAdd(&a.ctrl->z_count, 1ull);
         }
     }

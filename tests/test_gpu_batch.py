@@ -38,7 +38,7 @@ def make_batch(env, sets, **kw):
 
 def test_batch_chains_follow_the_oracle(env, orc):
     ds, b = make_batch(env, SETS, seed=9, chain_id=3, debug_store_z=True)
-    assert len(b) == 6
+    assert len(b) == sum(c for _, _, c in SETS)
     ors = []
     cid = 3
     for d, xt, c in ds:
