@@ -617,8 +617,13 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 __device__ bool factor_diag(Tile& S, Tile& T, uint64_t* rec) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double* flag = &T[kTile - 1][kTile];  // padding corner, not part of the tile
-    for (int e = threadIdx.x; e < kTile * kTile; e += kThreads) T[e / kTile][e % kTile] = e / kTile == e % kTile ? 1.0 : 0.0;
-    __syncthreads();
+    // T starts as the identity: wave 0 makes its first panel's rows in
+    // registers, the other waves write rows 16.. meanwhile (the first
+    // barrier below orders them before any reader).
+    if (wave > 0)
+        for (int e = threadIdx.x - kWave + 16 * kTile; e < kTile * kTile; e += kThreads - kWave)
+            T[e / kTile][e % kTile] = e / kTile == e % kTile ? 1.0 : 0.0;
+#pragma unroll
     for (int P = 0; P < 4; ++P) {
         const int r0 = 16 * P;
         if (wave == 0) {
@@ -626,7 +631,7 @@ __device__ bool factor_diag(Tile& S, Tile& T, uint64_t* rec) {
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
                 a[c] = S[r0 + c][lane];
-                w[c] = T[r0 + c][lane];
+                w[c] = P == 0 ? (lane == c ? 1.0 : 0.0) : T[r0 + c][lane];
             }
             bool ok = true;
             double d = rdlane(a[0], r0);
