@@ -44,6 +44,14 @@ constexpr int kSmallP = 16;            // p up to this runs the one-block p-side
 #endif
 constexpr int kMaxGroup = HSP_MAX_GROUP;  // most blocks of the p-side group
 constexpr int kZGroup = 16;            // z-pass blocks whose partials one block sums
+#ifndef HSP_Z_STATIC_PCT
+#define HSP_Z_STATIC_PCT 40
+#endif
+#ifndef HSP_Z_UNIT
+#define HSP_Z_UNIT 8
+#endif
+constexpr int kZStaticPct = HSP_Z_STATIC_PCT;  // share of the z-pass tiles dealt out statically
+constexpr int kZUnit = HSP_Z_UNIT;             // tiles per claimed unit of the remainder
 // LDS of one sweep-kernel block: two 64 x 66 float64 tiles (67,584 bytes; rows
 // 16-byte aligned).  The same buffer holds the z pass's reduction segment and
 // the packed Q of the one-block path (p (p + 1) / 2 <= 8256 doubles).
@@ -64,6 +72,7 @@ struct Ctrl {
     alignas(128) unsigned long long bar_count;  // arrivals at p-side group barriers (monotonic)
     alignas(128) unsigned long long z_count;    // z-pass groups finished (monotonic)
     alignas(128) uint32_t task_next;  // next factorisation task of the shared queue (zero between launches)
+    alignas(128) uint32_t z_next;     // next z-pass unit of the shared remainder (zero between launches)
 };
 
 enum : uint32_t {

@@ -1061,6 +1061,7 @@ __device__ __forceinline__ void pside_role(Args& a, uint32_t rank, uint32_t k, d
             for (uint32_t e = threadIdx.x; e < 2 * nt * nt; e += kThreads) a.ver[e] = 0u;
             if (threadIdx.x == 0) a.ctrl->task_next = 0u;
         }
+        if ((a.mode & kModeZ) && threadIdx.x == 0) a.ctrl->z_next = 0u;
         __threadfence();
     }
 }

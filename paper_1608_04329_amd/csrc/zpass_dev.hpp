@@ -55,6 +55,15 @@ __device__ __forceinline__ uint32_t word_of(const uint4& v, int i) {
     return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
 }
 
+// A tile's float32 sum of x_ij z_i, rounded to a multiple of 2^-24 (for
+// |v| < 2^27).  Sums of such values below 2^29 in magnitude are exact in
+// float64, so X^T z does not depend on which block summed which rows or in
+// what order: the dynamically dealt tiles keep b bitwise reproducible.
+__device__ __forceinline__ double on_grid(double v) {
+    constexpr double kC = 0x1.8p28;  // 1.5 * 2^28: its float64 spacing is 2^-24
+    return (v + kC) - kC;
+}
+
 template <int XT>
 __device__ __forceinline__ float xelem(const uint4& v, int e) {
     if constexpr (XT == 0) {
@@ -109,7 +118,7 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
     uint32_t maxatt = 0;
     bool capped = false;
 
-    for (uint32_t t = zrank * kWPB + wave; t < n_tiles; t += W) {
+    auto tile = [&](uint32_t t) {
         const uint32_t row0 = t * R;
         uint4 xr[R][KC];
 #pragma unroll
@@ -203,8 +212,35 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
                 float acc = 0.0f;
 #pragma unroll
                 for (int r = 0; r < R; ++r) acc = fmaf(zr[r], xelem<XT>(xr[r][kc], e), acc);
-                bacc[kc][e] += (double)acc;
+                bacc[kc][e] += on_grid((double)acc);
             }
+    };
+
+    // Most tiles are dealt out statically, interleaved over all waves; the
+    // rest go out in units of kZUnit tiles to whichever block asks next, so
+    // blocks on busier CUs do less of them.  Thread 0 reserves the next unit
+    // before working on the current one.
+    const uint32_t n_static = (uint32_t)((uint64_t)n_tiles * kZStaticPct / 100 / W * W);
+    for (uint32_t t = zrank * kWPB + wave; t < n_static; t += W) tile(t);
+    if (n_static < n_tiles) {
+        const uint32_t n_units = (n_tiles - n_static + kZUnit - 1) / kZUnit;
+        double* slot = red;  // free until the reduction below
+        if (threadIdx.x == 0) *slot = (double)atomicAdd(&a.ctrl->z_next, 1u);
+        __syncthreads();
+        uint32_t u = (uint32_t)*slot;
+        __syncthreads();
+        while (u < n_units) {
+            uint32_t next = 0;
+            if (threadIdx.x == 0) next = atomicAdd(&a.ctrl->z_next, 1u);
+            for (uint32_t j = wave; j < (uint32_t)kZUnit; j += kWPB) {
+                const uint32_t t = n_static + u * kZUnit + j;
+                if (t < n_tiles) tile(t);
+            }
+            if (threadIdx.x == 0) *slot = (double)next;
+            __syncthreads();
+            u = (uint32_t)*slot;
+            __syncthreads();
+        }
     }
 
     // wave statistics
