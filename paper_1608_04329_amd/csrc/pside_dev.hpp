@@ -68,7 +68,7 @@ __device__ __forceinline__ void backoff(uint32_t& n, uint32_t cap) {
 }
 
 // Thread 0 only: wait until *ctr >= target, or give up after the timeout.
-// Relaxed polls; the caller orders its later reads with one acquire fence.
+// Relaxed polls; what the caller reads afterwards it loads coherently.
 __device__ __forceinline__ void wait_count(unsigned long long* ctr, unsigned long long target,
                                         Ctrl* ctrl, uint64_t timeout, uint32_t cap = 16) {
     const uint64_t t0 = wall_clock64();
@@ -82,19 +82,6 @@ __device__ __forceinline__ void wait_count(unsigned long long* ctr, unsigned lon
         }
         backoff(nap, cap);
     }
-}
-
-// Tiles that the factorisation's tasks hand to each other move through
-// device-coherent loads and stores (they bypass the non-coherent caches), so
-// a task needs no cache writeback or invalidate: its stores are complete once
-// every wave has waited for them, and the version it then publishes orders
-// them for the reader.  Fences here would flush or drop a whole XCD's L2 and
-// stall the z pass streaming through it.
-__device__ __forceinline__ double ldc(const double* p) {
-    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void stc(double* p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Thread 0: next trace timestamp, or a given value (diagnostics only).
@@ -154,12 +141,10 @@ __device__ __forceinline__ void group_sync(Group& g) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        fence_release();
         atomicAdd(&g.ctrl->bar_count, 1ull);
         if (g.size > 1)
             wait_count(&g.ctrl->bar_count, g.base + (unsigned long long)(g.n + 1) * g.size, g.ctrl,
                        g.timeout);
-        fence_acquire();
     }
     g.n++;
     stamp(g);
@@ -205,7 +190,7 @@ __device__ double hyper_lambda_tau(Args& a, uint32_t k, bool writer, double* red
             const Words4 w = draw_words(a.seed, j, k, kTagLambda, 0, a.chain);
             lam = -log(u01d(w.w0)) / rate;
             if (!isfinite(lam)) bad = true;
-            if (writer) a.lam_m2[j] = lam;
+            if (writer) stc(&a.lam_m2[j], lam);
         } else {
             lam = a.lam_m2[j];
         }
@@ -253,7 +238,7 @@ __device__ double hyper_lambda_tau(Args& a, uint32_t k, bool writer, double* red
     // the other blocks may still be reading the old value: the new one goes to
     // a scratch slot and is published when the launch closes
     if (writer && threadIdx.x == 0) {
-        a.vec[2 * p] = tau;
+        stc(&a.vec[2 * p], tau);
         if (!isfinite(tau) || !(tau > 0.0)) atomicOr(&a.ctrl->err, kErrNonFinite);
     }
     __syncthreads();
@@ -273,7 +258,7 @@ __device__ void hyper_nu_xi(Args& a, uint32_t k) {
     const uint32_t p = a.x.p;
     for (uint32_t j = threadIdx.x; j < p; j += kThreads) {
         const Words4 w = draw_words(a.seed, j, k, kTagNu, 0, a.chain);
-        a.nu_m1[j] = -log(u01d(w.w0)) / (1.0 + a.lam_m2[j]);
+        a.nu_m1[j] = -log(u01d(w.w0)) / (1.0 + ldc(&a.lam_m2[j]));
     }
     if (threadIdx.x == 0) {
         const Words4 w = draw_words(a.seed, 0, k, kTagXi, 0, a.chain);
@@ -374,14 +359,13 @@ __device__ void small_path(Args& a, Group& g, uint32_t k, double* lds) {
     if (a.mode & kModeZ) {
         if (threadIdx.x == 0) {
             wait_count(&a.ctrl->z_count, g.zbase + a.zgroups, a.ctrl, a.timeout_ticks, 64);
-            fence_acquire();
         }
         __syncthreads();
         // one column per thread, summed over the group partial rows in order;
         // wave 0 takes b from LDS below
         for (uint32_t j = threadIdx.x; j < p; j += kThreads) {
             double s = 0.0;
-            for (uint32_t r = 0; r < a.zgroups; ++r) s += a.gpartial[(size_t)r * a.x.ld + j];
+            for (uint32_t r = 0; r < a.zgroups; ++r) s += ldc(&a.gpartial[(size_t)r * a.x.ld + j]);
             a.b[j] = s;
             lds[kSmallBOff + j] = s;
         }
@@ -424,7 +408,7 @@ __device__ void small_path(Args& a, Group& g, uint32_t k, double* lds) {
     if (keep) {
         __syncthreads();
         if (a.ring_lam)
-            for (uint32_t j = threadIdx.x; j < p; j += kThreads) a.ring_lam[(size_t)slot * p + j] = a.lam_m2[j];
+            for (uint32_t j = threadIdx.x; j < p; j += kThreads) a.ring_lam[(size_t)slot * p + j] = ldc(&a.lam_m2[j]);
         if (threadIdx.x == 0) a.ring_tau[slot] = current_tau(a);
     }
 }
@@ -454,7 +438,7 @@ __device__ __forceinline__ void load_tile(Tile& T, const double* M, uint32_t P, 
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const uint32_t gi = r0 + rb + 4 * q;
-            if (gi == c0 + c && gi < p) v[q] += tau * lam[gi];
+            if (gi == c0 + c && gi < p) v[q] += tau * ldc(lam + gi);
         }
     }
 #pragma unroll
@@ -544,7 +528,7 @@ __device__ __forceinline__ void load_tile_m(MTile& o, const double* M, uint32_t 
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const uint32_t gi = ri + 16 * bi + 4 * r, gj = cj + 16 * bj;
-                    if (gi == gj && gi < p) o.v[bi][bj][r] += tau * lam[gi];
+                    if (gi == gj && gi < p) o.v[bi][bj][r] += tau * ldc(lam + gi);
                 }
     }
 }
@@ -891,7 +875,7 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
         if (a.mode & kModeBeta)
             for (uint32_t i = threadIdx.x; i < p; i += kThreads) {
                 const Words4 w = draw_words(a.seed, i, k, kTagBetaS, 0, a.chain);
-                s_noise[i] = box_muller_d(u01d(w.w0), u01d(w.w1));
+                stc(&s_noise[i], box_muller_d(u01d(w.w0), u01d(w.w1)));
             }
     }
 
@@ -907,7 +891,6 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
     if (a.mode & kModeZ) {
         if (threadIdx.x == 0) {
             wait_count(&a.ctrl->z_count, g.zbase + a.zgroups, a.ctrl, a.timeout_ticks, 64);
-            fence_acquire();
         }
         if (g.trace && threadIdx.x == 0) g.trace[kTraceSlots - 1] = wall_clock64();
         __syncthreads();
@@ -926,7 +909,7 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
                     double v[8];
 #pragma unroll
                     for (int q = 0; q < 8; ++q)
-                        v[q] = r0 + q < a.zgroups ? gcol[(size_t)(r0 + q) * a.x.ld] : 0.0;
+                        v[q] = r0 + q < a.zgroups ? ldc(gcol + (size_t)(r0 + q) * a.x.ld) : 0.0;
 #pragma unroll
                     for (int q = 0; q < 8; ++q) s += v[q];
                 }
@@ -958,7 +941,7 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
                 for (int u = 0; u < 4; ++u) {
                     bj[u] = bl[j + 64 * u];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) x[u][r] = L0[(size_t)r * P + j + 64 * u];
+                    for (int r = 0; r < 4; ++r) x[u][r] = ldc(L0 + (size_t)r * P + j + 64 * u);
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
@@ -968,7 +951,7 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
             for (; j < jn; j += 64) {
                 const double bj = bl[j];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r] = fma(L0[(size_t)r * P + j], bj, acc[r]);
+                for (int r = 0; r < 4; ++r) acc[r] = fma(ldc(L0 + (size_t)r * P + j), bj, acc[r]);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -978,7 +961,7 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
                 double yi = acc[0];
 #pragma unroll
                 for (int r = 1; r < 4; ++r) yi = lane == r ? acc[r] : yi;
-                yv[i0 + lane] = yi + s_noise[i0 + lane];
+                stc(&yv[i0 + lane], yi + ldc(&s_noise[i0 + lane]));
             }
         }
         group_sync(g);
@@ -988,7 +971,7 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
         // every block reads about the same number of rows; 16 row groups per
         // column, four rows of loads in flight each.
         double* yl = lds;
-        for (uint32_t j = threadIdx.x; j < P; j += kThreads) yl[j] = j < p ? yv[j] : 0.0;
+        for (uint32_t j = threadIdx.x; j < P; j += kThreads) yl[j] = j < p ? ldc(&yv[j]) : 0.0;
         double* red = lds + P;
         __syncthreads();
         bool keep;
@@ -1005,8 +988,8 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
                 uint32_t i = cb + tr;
                 for (; i + 48 < P; i += 64)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) acc[u] = fma(Lc[(size_t)(i + 16 * u) * P], yl[i + 16 * u], acc[u]);
-                for (; i < P; i += 16) acc[0] = fma(Lc[(size_t)i * P], yl[i], acc[0]);
+                    for (int u = 0; u < 4; ++u) acc[u] = fma(ldc(Lc + (size_t)(i + 16 * u) * P), yl[i + 16 * u], acc[u]);
+                for (; i < P; i += 16) acc[0] = fma(ldc(Lc + (size_t)i * P), yl[i], acc[0]);
                 red[tr * 17 + tc] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
                 __syncthreads();
                 if (tr == 0 && col < p) {
@@ -1017,7 +1000,7 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
                     if (!isfinite(bi)) nonfinite = true;
                     if (keep) {
                         a.ring_beta[(size_t)slot * p + col] = bi;
-                        if (a.ring_lam) a.ring_lam[(size_t)slot * p + col] = a.lam_m2[col];
+                        if (a.ring_lam) a.ring_lam[(size_t)slot * p + col] = ldc(&a.lam_m2[col]);
                     }
                 }
                 __syncthreads();

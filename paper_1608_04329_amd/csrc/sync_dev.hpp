@@ -1,25 +1,24 @@
-// Cross-block ordering inside the sweep kernel (agent scope).
+// Hand-offs between blocks inside the sweep kernel.
 //
-// One thread of a block fences for the whole block: every wave first waits
-// for its own stores (s_waitcnt) and the block meets at a barrier; then the
-// thread writes this XCD's L2 back before it signals (release), or, having
-// seen a signal, invalidates the caches before the barrier that lets the
-// block's waves read (acquire).  The write-back and the invalidate are memory
-// operations of their own: the thread waits for each to complete, so the
-// signal cannot overtake the write-back and the other waves' loads cannot
-// overtake the invalidate.
+// Data that one block hands to another within a launch (factorisation tiles,
+// partial sums of X^T z, lambda^-2, the noise and y vectors) moves only
+// through device-coherent loads and stores (relaxed atomics at agent scope,
+// which bypass the caches that are not coherent across XCDs).  A hand-off
+// then needs no cache maintenance: the writer's waves wait for their own
+// stores (s_waitcnt) and meet at a barrier before one thread signals (a
+// counter or a tile version), and the reader loads only after it has seen
+// the signal.  Agent-scope fences would instead write back or invalidate a
+// whole XCD's L2 (and must then also be waited for), stalling the z pass
+// that streams through the same L2.
 #pragma once
 
 namespace hsp {
 
-__device__ __forceinline__ void fence_release() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __builtin_amdgcn_s_waitcnt(0);
+__device__ __forceinline__ double ldc(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-
-__device__ __forceinline__ void fence_acquire() {
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    __builtin_amdgcn_s_waitcnt(0);
+__device__ __forceinline__ void stc(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace hsp

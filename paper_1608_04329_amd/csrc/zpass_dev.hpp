@@ -268,26 +268,23 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
             double v = red[c];
 #pragma unroll
             for (int w = 1; w < kWPB; ++w) v += red[w * kRedCols + c];
-            a.partial[(size_t)zrank * ld + seg + c] = v;
+            stc(&a.partial[(size_t)zrank * ld + seg + c], v);
         }
         __syncthreads();
     }
     // This block's partial is complete.  The last of each group of kZGroup
     // consecutive blocks to finish adds the group's partials in block order
     // (deterministic) and publishes the group sum; the p-side waits for all
-    // groups.  Every wave waits for its own stores; one thread writes the
-    // cache back before arriving, and the last arriver invalidates before
-    // reading the others' partials.
+    // groups.  Partials and group sums move through coherent stores and
+    // loads: every wave waits for its own stores before the block arrives.
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     const uint32_t grp = zrank / kZGroup;
     const uint32_t g0 = grp * kZGroup;
     const uint32_t gsize = min((uint32_t)kZGroup, nz - g0);
     if (threadIdx.x == 0) {
-        fence_release();
         const uint32_t old = atomicAdd(&a.zgrp_count[grp], 1u);
         const bool lst = old == gsize - 1;
-        if (lst) fence_acquire();
         red[0] = lst ? 1.0 : 0.0;
     }
     __syncthreads();
@@ -298,17 +295,17 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
             double v[kZGroup];
 #pragma unroll
             for (int r = 0; r < kZGroup; ++r)
-                v[r] = (uint32_t)r < gsize ? a.partial[(size_t)(g0 + r) * ld + c] : 0.0;
+                v[r] = (uint32_t)r < gsize ? ldc(&a.partial[(size_t)(g0 + r) * ld + c]) : 0.0;
             double s = v[0];
 #pragma unroll
             for (int r = 1; r < kZGroup; ++r) s += v[r];
-            a.gpartial[(size_t)grp * ld + c] = s;
+            stc(&a.gpartial[(size_t)grp * ld + c], s);
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0) {
-            a.zgrp_count[grp] = 0u;  // every block of the group has arrived
-            fence_release();
+            // every block of the group has arrived
+            __hip_atomic_store(&a.zgrp_count[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             atomicAdd(&a.ctrl->z_count, 1ull);
         }
     }
