@@ -40,7 +40,7 @@ constexpr int kThreads = 256;          // threads per block of the sweep kernel
 constexpr int kTile = 64;              // p-side tile edge
 constexpr int kSmallP = 16;            // p up to this runs the one-block p-side path
 #ifndef HSP_MAX_GROUP
-#define HSP_MAX_GROUP 32
+#define HSP_MAX_GROUP 48
 #endif
 constexpr int kMaxGroup = HSP_MAX_GROUP;  // most blocks of the p-side group
 constexpr int kZGroup = 16;            // z-pass blocks whose partials one block sums
