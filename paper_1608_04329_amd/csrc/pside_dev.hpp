@@ -897,28 +897,45 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
     }
     // b = X^T z into LDS (zero on the padding): every block sums the z groups'
     // partials itself, rows in ascending order, so all hold the same b and no
-    // barrier is needed; block 0 also stores it.  Eight rows of loads are in
-    // flight per column.
+    // barrier is needed; block 0 also stores it.  A thread takes four columns
+    // at once, eight rows each: 32 coherent loads in flight.
     double* bl = lds;
-    for (uint32_t j = threadIdx.x; j < P; j += kThreads) {
-        double s = 0.0;
-        if (j < p) {
-            if (a.mode & kModeZ) {
-                const double* gcol = a.gpartial + j;
-                for (uint32_t r0 = 0; r0 < a.zgroups; r0 += 8) {
-                    double v[8];
+    for (uint32_t j0 = threadIdx.x; j0 < P; j0 += 4 * kThreads) {
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        if (a.mode & kModeZ) {
+            for (uint32_t r0 = 0; r0 < a.zgroups; r0 += 8) {
+                double v[4][8];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        v[q] = r0 + q < a.zgroups ? ldc(gcol + (size_t)(r0 + q) * a.x.ld) : 0.0;
+                for (int c = 0; c < 4; ++c)
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) s += v[q];
-                }
-                if (rank == 0) a.b[j] = s;
-            } else {
-                s = a.b[j];
+                    for (int q = 0; q < 8; ++q) {
+                        const uint32_t j = j0 + c * kThreads;
+                        v[c][q] = (j < p && r0 + q < a.zgroups)
+                                      ? ldc(a.gpartial + (size_t)(r0 + q) * a.x.ld + j)
+                                      : 0.0;
+                    }
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) s[c] += v[c][q];
             }
         }
-        bl[j] = s;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t j = j0 + c * kThreads;
+            if (j < P) {
+                double sj = 0.0;
+                if (j < p) {
+                    if (a.mode & kModeZ) {
+                        sj = s[c];
+                        if (rank == 0) a.b[j] = sj;
+                    } else {
+                        sj = a.b[j];
+                    }
+                }
+                bl[j] = sj;
+            }
+        }
     }
     __syncthreads();
 
@@ -986,6 +1003,15 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
                 const double* Lc = a.Linv + col;
                 double acc[4] = {0.0, 0.0, 0.0, 0.0};
                 uint32_t i = cb + tr;
+                // sixteen loads in flight; the same accumulation order as
+                // the four-row loop below
+                for (; i + 240 < P; i += 256) {
+                    double x[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) x[u] = ldc(Lc + (size_t)(i + 16 * u) * P);
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) acc[u & 3] = fma(x[u], yl[i + 16 * u], acc[u & 3]);
+                }
                 for (; i + 48 < P; i += 64)
 #pragma unroll
                     for (int u = 0; u < 4; ++u) acc[u] = fma(ldc(Lc + (size_t)(i + 16 * u) * P), yl[i + 16 * u], acc[u]);
