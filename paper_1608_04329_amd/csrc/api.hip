@@ -557,7 +557,7 @@ hsp_status plan_packs(hsp_batch* b) {
         if (cap < 2) return batch_fail(b, HSP_EHIP, "no resident capacity for a pack");
         const double bw = 7.0e6 / cap;  // bytes per microsecond per block (about 7 TB/s in all)
         std::vector<ChainCost> cost(b->chains.size());
-        const int rows = chunks <= 4 ? 8 : (chunks <= 8 ? 4 : 2);
+        const int rows = rows_for_chunks(chunks);
         for (size_t i : ids) {
             const hsp_state* s = b->chains[i];
             ChainCost& c = cost[i];

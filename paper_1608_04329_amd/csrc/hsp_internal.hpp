@@ -50,6 +50,9 @@ constexpr int kZGroup = 16;            // z-pass blocks whose partials one block
 #ifndef HSP_Z_UNIT
 #define HSP_Z_UNIT 8
 #endif
+// Rows per wave tile of the z pass for rows of kc 16-byte chunks per lane
+// (the register budget: taller tiles for kc <= 2 spill).
+constexpr int rows_for_chunks(int kc) { return kc <= 4 ? 8 : (kc <= 8 ? 4 : 2); }
 constexpr int kZStaticPct = HSP_Z_STATIC_PCT;  // share of the z-pass tiles dealt out statically
 constexpr int kZUnit = HSP_Z_UNIT;             // tiles per claimed unit of the remainder
 // LDS of one sweep-kernel block: two 64 x 66 float64 tiles (67,584 bytes; rows

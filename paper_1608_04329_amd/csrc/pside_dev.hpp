@@ -807,9 +807,11 @@ __device__ bool run_tasks(Args& a, Group& g, uint32_t rank, double tau, Tile& S,
                 put_tile_m(a.A, P, r1, k0, acc, 1.0, zero);
                 __syncthreads();
                 acc_to_lds(S, acc, 1.0, zero);
-                publish(&vU[km * nt + kb], kb);
-                gemm_tn(S, S, acc);
                 __syncthreads();
+                gemm_tn(S, S, acc);
+                // U_{k-1,k} is published once its stores are complete; the
+                // product above hid their latency
+                publish(&vU[km * nt + kb], kb);
                 acc_to_lds(S, acc, -1.0, dg);
                 __syncthreads();
             }
@@ -1039,9 +1041,6 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
 
 // The whole p-side role of block `rank` of the group.
 __device__ __forceinline__ void pside_role(Args& a, uint32_t rank, uint32_t k, double* lds) {
-    // The group's waves share SIMDs with z-pass waves; their latency-bound
-    // chain gets the higher issue priority.
-    __builtin_amdgcn_s_setprio(3);
     Group g;
     g.trace = a.trace ? a.trace + (size_t)rank * kTraceSlots : nullptr;
     if (g.trace && threadIdx.x == 0) g.trace[0] = wall_clock64();

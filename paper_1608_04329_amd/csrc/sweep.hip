@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(const SweepArgs* con
     run_block<XT, KC, R>(*(Args*)args[c], lds);
 }
 
-constexpr int rows_for_chunks(int kc) { return kc <= 4 ? 8 : (kc <= 8 ? 4 : 2); }
+
 
 using KernelFn = void (*)(const SweepArgs* const*, const uint16_t*);
 
