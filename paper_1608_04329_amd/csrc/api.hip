@@ -30,7 +30,7 @@ struct hsp_state {
     Ctrl* ctrl = nullptr;
     double *beta = nullptr, *lam = nullptr, *nu = nullptr, *tau = nullptr, *xi = nullptr;
     double *b = nullptr, *G = nullptr, *Gp = nullptr, *A = nullptr, *Linv = nullptr;
-    double *vec = nullptr, *partial = nullptr, *gpartial = nullptr;
+    double *vec = nullptr, *partial = nullptr, *bsum = nullptr;
     uint32_t* zgrp_count = nullptr;
     uint32_t *tasks = nullptr, *task_off = nullptr, *ver = nullptr;  // tile path schedule
     float* beta32 = nullptr;
@@ -91,7 +91,7 @@ SweepArgs sweep_args(hsp_state* s, uint32_t mode) {
     a.y = dev_ptr(s->y);
     a.beta32 = dev_ptr(s->beta32);
     a.partial = dev_ptr(s->partial);
-    a.gpartial = dev_ptr(s->gpartial);
+    a.bsum = dev_ptr(s->bsum);
     a.zgrp_count = dev_ptr(s->zgrp_count);
     a.zdbg = dev_ptr(s->opt.debug_store_z ? s->zdbg : nullptr);
     a.adbg = dev_ptr(s->opt.debug_store_z ? s->adbg : nullptr);
@@ -192,7 +192,7 @@ void free_state(hsp_state* s) {
     }
     void* bufs[] = {s->Xbuf, s->y, s->ctrl, s->beta, s->lam, s->nu, s->tau, s->xi, s->b, s->G, s->Gp,
                     s->A, s->Linv, s->vec, s->partial, s->beta32, s->zdbg, s->adbg,
-                    s->ring_beta, s->ring_tau, s->ring_lam, s->trace, s->gpartial,
+                    s->ring_beta, s->ring_tau, s->ring_lam, s->trace, s->bsum,
                     s->zgrp_count, s->dargs, s->dtab, s->tasks, s->task_off, s->ver};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
@@ -361,7 +361,8 @@ hsp_status chain_impl(hsp_state* s) {
     HIP_TRY(dalloc(&s->partial, (size_t)s->plan.gz * ld));
     {
         const size_t ng = (s->plan.gz + kZGroup - 1) / kZGroup;
-        HIP_TRY(dalloc(&s->gpartial, ng * ld));
+        HIP_TRY(dalloc(&s->bsum, ld));
+        HIP_TRY(hipMemsetAsync(s->bsum, 0, ld * sizeof(double), s->stream));
         HIP_TRY(dalloc(&s->zgrp_count, ng));
         HIP_TRY(hipMemsetAsync(s->zgrp_count, 0, ng * sizeof(uint32_t), s->stream));
     }

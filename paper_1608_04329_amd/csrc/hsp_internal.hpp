@@ -113,7 +113,7 @@ struct SweepArgs {
     HSP_GLOBAL const uint8_t* y;
     HSP_GLOBAL float* beta32;      // ld floats (padding zero): beta for the z pass
     HSP_GLOBAL double* partial;    // gz x ld: per-block float64 partials of X^T z
-    HSP_GLOBAL double* gpartial;   // zgroups x ld: sums of kZGroup consecutive block partials
+    HSP_GLOBAL double* bsum;       // ld: X^T z accumulated by the z groups (zero between launches)
     HSP_GLOBAL uint32_t* zgrp_count;  // zgroups arrival counters (zero between launches)
     HSP_GLOBAL float* zdbg;        // optional: z of the last z pass (N)
     HSP_GLOBAL int32_t* adbg;      // optional: accepted proposal | gauss bit (N)

@@ -361,11 +361,9 @@ __device__ void small_path(Args& a, Group& g, uint32_t k, double* lds) {
             wait_count(&a.ctrl->z_count, g.zbase + a.zgroups, a.ctrl, a.timeout_ticks, 64);
         }
         __syncthreads();
-        // one column per thread, summed over the group partial rows in order;
-        // wave 0 takes b from LDS below
+        // b as the z groups accumulated it; wave 0 takes it from LDS below
         for (uint32_t j = threadIdx.x; j < p; j += kThreads) {
-            double s = 0.0;
-            for (uint32_t r = 0; r < a.zgroups; ++r) s += ldc(&a.gpartial[(size_t)r * a.x.ld + j]);
+            const double s = ldc(&a.bsum[j]);
             a.b[j] = s;
             lds[kSmallBOff + j] = s;
         }
@@ -897,47 +895,20 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
         if (g.trace && threadIdx.x == 0) g.trace[kTraceSlots - 1] = wall_clock64();
         __syncthreads();
     }
-    // b = X^T z into LDS (zero on the padding): every block sums the z groups'
-    // partials itself, rows in ascending order, so all hold the same b and no
-    // barrier is needed; block 0 also stores it.  A thread takes four columns
-    // at once, eight rows each: 32 coherent loads in flight.
+    // b = X^T z into LDS (zero on the padding), as the z groups accumulated
+    // it; block 0 also stores it.
     double* bl = lds;
-    for (uint32_t j0 = threadIdx.x; j0 < P; j0 += 4 * kThreads) {
-        double s[4] = {0.0, 0.0, 0.0, 0.0};
-        if (a.mode & kModeZ) {
-            for (uint32_t r0 = 0; r0 < a.zgroups; r0 += 8) {
-                double v[4][8];
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const uint32_t j = j0 + c * kThreads;
-                        v[c][q] = (j < p && r0 + q < a.zgroups)
-                                      ? ldc(a.gpartial + (size_t)(r0 + q) * a.x.ld + j)
-                                      : 0.0;
-                    }
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) s[c] += v[c][q];
+    for (uint32_t j = threadIdx.x; j < P; j += kThreads) {
+        double s = 0.0;
+        if (j < p) {
+            if (a.mode & kModeZ) {
+                s = ldc(&a.bsum[j]);
+                if (rank == 0) a.b[j] = s;
+            } else {
+                s = a.b[j];
             }
         }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const uint32_t j = j0 + c * kThreads;
-            if (j < P) {
-                double sj = 0.0;
-                if (j < p) {
-                    if (a.mode & kModeZ) {
-                        sj = s[c];
-                        if (rank == 0) a.b[j] = sj;
-                    } else {
-                        sj = a.b[j];
-                    }
-                }
-                bl[j] = sj;
-            }
-        }
+        bl[j] = s;
     }
     __syncthreads();
 
@@ -1069,7 +1040,12 @@ __device__ __forceinline__ void pside_role(Args& a, uint32_t rank, uint32_t k, d
             for (uint32_t e = threadIdx.x; e < 2 * nt * nt; e += kThreads) a.ver[e] = 0u;
             if (threadIdx.x == 0) a.ctrl->task_next = 0u;
         }
-        if ((a.mode & kModeZ) && threadIdx.x == 0) a.ctrl->z_next = 0u;
+        if (a.mode & kModeZ) {
+            // every block of the group has read b's accumulator (before the
+            // barrier that follows y): clear it for the next launch
+            if (threadIdx.x == 0) a.ctrl->z_next = 0u;
+            for (uint32_t j = threadIdx.x; j < a.x.ld; j += kThreads) stc(&a.bsum[j], 0.0);
+        }
         __threadfence();
     }
 }

@@ -274,7 +274,7 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
     }
     // This block's partial is complete.  The last of each group of kZGroup
     // consecutive blocks to finish adds the group's partials in block order
-    // (deterministic) and publishes the group sum; the p-side waits for all
+    // and adds the group sum into b's accumulator; the p-side waits for all
     // groups.  Partials and group sums move through coherent stores and
     // loads: every wave waits for its own stores before the block arrives.
     __builtin_amdgcn_s_waitcnt(0);
@@ -299,7 +299,9 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
             double s = v[0];
 #pragma unroll
             for (int r = 1; r < kZGroup; ++r) s += v[r];
-            stc(&a.gpartial[(size_t)grp * ld + c], s);
+            // on the 2^-24 grid below 2^29 the float64 atomic additions are
+            // exact, so the groups' order of arrival does not matter
+            __hip_atomic_fetch_add(&a.bsum[c], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
