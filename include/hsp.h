@@ -21,7 +21,11 @@
  * Random numbers: Philox4x32-10 with key = seed and counter
  * (index, sweep number k >= 1, tag << 24 | round, chain id).  A state's
  * draws are a pure function of (X, y, seed, chain id, starting state), so
- * runs are bit-reproducible and resumable.
+ * runs are bit-reproducible and resumable.  (X^T z is accumulated on a 2^-24
+ * grid, where float64 sums are exact in any order, so the GPU's dynamic
+ * split of rows between blocks does not change it; this holds while every
+ * |(X^T z)_j| stays below 2^29.  Beyond that the results keep float64
+ * accuracy but may differ in the last bits between runs.)
  *
  * Conventions shared by every entry point:
  *  - Every call returns an hsp_status and never aborts or throws.
