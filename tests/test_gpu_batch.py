@@ -71,6 +71,31 @@ def test_batch_chains_follow_the_oracle(env, orc):
     b.close()
 
 
+def test_batch_chain_equals_lone_chain(env):
+    """A chain in a pack (its own group and z-block counts) draws bitwise what
+    the same chain draws alone: X^T z is exact in any split of the rows, and
+    the p-side's arithmetic does not depend on its group size."""
+    torch, hsp = env
+    ds, b = make_batch(env, SETS, seed=4, chain_id=5, record_lambda=True)
+    b.sweep(4)
+    b.sync()
+    batch = [b.chain(i).draws() for i in range(len(b))]
+    b.close()
+    i = 0
+    for d, xt, c in ds:
+        for _ in range(c):
+            s = hsp.Sampler(torch.from_numpy(d.X).cuda(), torch.from_numpy(d.y).cuda(), seed=4,
+                            chain_id=5 + i, x_type=xt, record_lambda=True)
+            s.sweep(4)
+            s.sync()
+            bb, tb, lb, nb = batch[i]
+            bl, tl, ll, nl = s.draws()
+            s.close()
+            assert nb == nl == 4
+            assert np.array_equal(bb, bl) and np.array_equal(tb, tl) and np.array_equal(lb, ll), (i, d.p, xt)
+            i += 1
+
+
 def test_batch_is_reproducible(env):
     outs = []
     for _ in range(2):
