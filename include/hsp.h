@@ -21,11 +21,17 @@
  * Random numbers: Philox4x32-10 with key = seed and counter
  * (index, sweep number k >= 1, tag << 24 | round, chain id).  A state's
  * draws are a pure function of (X, y, seed, chain id, starting state), so
- * runs are bit-reproducible and resumable.  (X^T z is accumulated on a 2^-24
- * grid, where float64 sums are exact in any order, so the GPU's dynamic
- * split of rows between blocks does not change it; this holds while every
- * |(X^T z)_j| stays below 2^29.  Beyond that the results keep float64
- * accuracy but may differ in the last bits between runs.)
+ * runs are bit-reproducible and resumable.  (The library stores column j of
+ * X multiplied by 2^-e_j, the power of two that brings its largest
+ * magnitude into (1/2, 1]; an exact scaling that leaves every product
+ * x_ij beta_j unchanged.  X^T z is accumulated from float32 sums over a few
+ * rows, each rounded to a multiple of 2^-24 in those column units, where
+ * float64 sums are exact in any order, so the GPU's dynamic split of rows
+ * between blocks does not change it and its rounding follows each column's
+ * scale.  Exactness holds while sum_i |z_i| < 2^29; beyond that the results
+ * keep float64 accuracy but may differ in the last bits between runs.
+ * Entries below 2^-126 of their column's largest magnitude lose precision
+ * to float32 subnormals.)
  *
  * Conventions shared by every entry point:
  *  - Every call returns an hsp_status and never aborts or throws.
@@ -100,6 +106,23 @@ hsp_status hsp_create(const float* X, const uint8_t* y, int64_t N, int64_t p,
 int64_t hsp_max_p(void);
 
 /*
+ * G = X^T X in float64 (Section 5, beta step i: the one-time product the
+ * precision matrix Q = X^T X + tau^-2 Lambda^-2 is built from) for a design
+ * on the device.  X: N x p, row-major with leading dimension ld >= p
+ * elements, float32 (x_type HSP_X_F32) or bfloat16 bit patterns (HSP_X_BF16,
+ * uint16 per element); every element is widened exactly to float64 and the
+ * products are summed on the FP64 matrix cores in a fixed order (the same G,
+ * bit for bit, on every call).  G: device buffer of p x p doubles, row-major,
+ * written whole (symmetric).  Allocates a device workspace of about
+ * 32 KB x (64-wide tile pairs of G) x (row splits) and frees it before
+ * returning; runs on hip_stream (NULL: the null stream) and waits for it.
+ * Errors: HSP_EINVAL (NULL pointers, N < 1, p < 1, ld < p, N or ld >= 2^32,
+ * unknown x_type); HSP_ENOMEM; HSP_EHIP.
+ */
+hsp_status hsp_gram(const void* X, int32_t x_type, int64_t N, int64_t p, int64_t ld, double* G,
+                    void* hip_stream);
+
+/*
  * Enqueue n_iter full sweeps on the state's stream and return without
  * waiting.  Sweep k draws, in order: z and lambda^-2 from beta^(k-1), then
  * tau^-2; then beta, nu^-1 and xi^-1 (Section 5, updates (i)-(ii)), and
@@ -167,8 +190,9 @@ hsp_status hsp_batch_chain(hsp_batch* b, int64_t i, hsp_state** chain);
 hsp_status hsp_batch_sweep(hsp_batch* b, int64_t n_iter);
 /* Wait for the batch's work and report the first chain's device failure. */
 hsp_status hsp_batch_sync(hsp_batch* b);
-/* Timing of the batched sweeps enqueued while enabled (HIP events on the
- * batch's stream around each graph replay): mean ms per batched sweep. */
+/* Timing of the batched sweeps enqueued while enabled (a pair of HIP events
+ * on the batch's stream around each graph replay, at most 256 pairs in use
+ * as for hsp_set_timing): mean ms per batched sweep. */
 hsp_status hsp_batch_set_timing(hsp_batch* b, int32_t enable);
 hsp_status hsp_batch_get_timing(hsp_batch* b, double* ms_per_sweep, int64_t* n_sweeps);
 /* Text of the batch's last failure (never NULL; NULL batch: the last failed
@@ -214,10 +238,13 @@ hsp_status hsp_get_gram(hsp_state* s, double* G);
  * the largest number of truncated-normal proposals any row needed. */
 hsp_status hsp_get_counters(hsp_state* s, uint64_t* lambda_clamps, uint32_t* max_attempts);
 
-/* Timing of the kernels of the last sweeps enqueued by hsp_sweep, measured
- * with HIP events on the state's stream: mean milliseconds per sweep of the
- * z pass (the dominant N x p kernel) and of the whole sweep.  Enable with
- * hsp_set_timing(s, 1) before hsp_sweep (sweeps then run without a graph). */
+/* Timing of the sweeps enqueued by hsp_sweep while enabled, measured with a
+ * pair of HIP events on the state's stream around each sweep's launch:
+ * zpass_ms = mean milliseconds per launch of the sweep kernel (z pass and
+ * p-side share it), sweep_ms = (first start to last end) / sweeps.  Enabling
+ * (hsp_set_timing(s, 1)) resets the counts.  At most 256 event pairs are in
+ * use: when they are, hsp_sweep waits for the oldest timed sweeps and adds
+ * their durations to a running sum. */
 hsp_status hsp_set_timing(hsp_state* s, int32_t enable);
 hsp_status hsp_get_timing(hsp_state* s, double* zpass_ms, double* sweep_ms, int64_t* n_sweeps);
 

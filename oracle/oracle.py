@@ -157,6 +157,24 @@ def gram(X):
     return G
 
 
+def gram_fast(X):
+    """G = X^T X by a library matmul over the exactly widened float64 X.
+
+    The same definition as gram() (Section 5, beta step i) with numpy's
+    summation order instead of the plain row loop; for designs too large for
+    the loop to finish in seconds.  Agreement with gram() is pinned in the
+    oracle tests.
+    """
+    if X.dtype == np.uint16:
+        Xf = (X.astype(np.uint32) << 16).view(np.float32)
+    elif X.dtype == np.float32:
+        Xf = X
+    else:
+        raise TypeError("X must be float32 or uint16 (bfloat16 bits)")
+    X64 = Xf.astype(np.float64)
+    return X64.T @ X64
+
+
 def gram_entry(X, j, k):
     px, xt, N, p = _xarg(X)
     return lib().orc_gram_entry(px, xt, N, p, j, k)
@@ -223,13 +241,25 @@ def beta_step(G, lam_m2, tau_m2, b, seed, sweep, chain=0):
 class Chain:
     """Markov state of one oracle chain (beta, lam^-2, nu^-1, tau^-2, xi^-1, sweep)."""
 
-    def __init__(self, p, beta=None, lam_m2=None, nu_m1=None, tau_m2=1.0, xi_m1=1.0, sweep=0):
+    def __init__(self, p, beta=None, lam_m2=None, nu_m1=None, tau_m2=None, xi_m1=None, sweep=0):
+        """The cold start of Section 6.1 (orc_cold_start) unless a state is given."""
         self.p = p
-        self.beta = np.zeros(p) if beta is None else _f64(beta).copy()
-        self.lam_m2 = np.ones(p) if lam_m2 is None else _f64(lam_m2).copy()
-        self.nu_m1 = np.ones(p) if nu_m1 is None else _f64(nu_m1).copy()
-        self.tau_m2 = float(tau_m2)
-        self.xi_m1 = float(xi_m1)
+        self.beta, self.lam_m2, self.nu_m1 = np.zeros(p), np.zeros(p), np.zeros(p)
+        self.tau_m2 = self.xi_m1 = 0.0
+        self.sweep = 0
+        st = self._cstate()
+        lib().orc_cold_start(p, C.byref(st))
+        self._pull(st)
+        if beta is not None:
+            self.beta = _f64(beta).copy()
+        if lam_m2 is not None:
+            self.lam_m2 = _f64(lam_m2).copy()
+        if nu_m1 is not None:
+            self.nu_m1 = _f64(nu_m1).copy()
+        if tau_m2 is not None:
+            self.tau_m2 = float(tau_m2)
+        if xi_m1 is not None:
+            self.xi_m1 = float(xi_m1)
         self.sweep = int(sweep)
 
     def _cstate(self):

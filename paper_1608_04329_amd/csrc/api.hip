@@ -16,7 +16,73 @@ using namespace hsp;
 
 namespace {
 thread_local std::string g_create_error;
-}
+
+// Launch timing with HIP events on one stream: a pair of events around each
+// timed launch, from a pool of kPairs pairs; when the pool is full its
+// durations are folded into a running sum (waiting for the last of them), so
+// a long timed run holds a bounded number of events.
+struct EventTimer {
+    static constexpr size_t kPairs = 256;
+    std::vector<hipEvent_t> pool;  // 2 kPairs events, created on first use
+    hipEvent_t first = nullptr;    // recorded before the first timed launch
+    size_t used = 0;               // pairs recorded since the last fold
+    size_t last = 0;               // pool index of the latest end event
+    double sum_ms = 0.0;           // durations of folded pairs
+    int64_t n = 0;                 // timed launches
+
+    hipError_t fold() {
+        if (!used) return hipSuccess;
+        hipError_t e = hipEventSynchronize(pool[2 * used - 1]);
+        for (size_t i = 0; !e && i < used; ++i) {
+            float ms = 0.0f;
+            e = hipEventElapsedTime(&ms, pool[2 * i], pool[2 * i + 1]);
+            sum_ms += ms;
+        }
+        used = 0;
+        return e;
+    }
+    hipError_t begin(hipStream_t st) {
+        if (pool.empty()) {
+            pool.assign(2 * kPairs, nullptr);
+            for (auto& e : pool)
+                if (hipError_t r = hipEventCreate(&e)) return r;
+            if (hipError_t r = hipEventCreate(&first)) return r;
+        }
+        if (used == kPairs)
+            if (hipError_t r = fold()) return r;
+        if (n == 0)
+            if (hipError_t r = hipEventRecord(first, st)) return r;
+        return hipEventRecord(pool[2 * used], st);
+    }
+    hipError_t end(hipStream_t st) {
+        last = 2 * used + 1;
+        ++used;
+        ++n;
+        return hipEventRecord(pool[last], st);
+    }
+    // Mean duration per launch and (first start to last end) / launches.
+    hipError_t result(double* mean_ms, double* span_ms, int64_t* count) {
+        *mean_ms = *span_ms = 0.0;
+        *count = n;
+        if (!n) return hipSuccess;
+        if (hipError_t e = fold()) return e;
+        float ms = 0.0f;
+        if (hipError_t e = hipEventElapsedTime(&ms, first, pool[last])) return e;
+        *mean_ms = sum_ms / n;
+        *span_ms = ms / n;
+        return hipSuccess;
+    }
+    void reset() {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        if (first) (void)hipEventDestroy(first);
+        pool.clear();
+        first = nullptr;
+        used = last = 0;
+        sum_ms = 0.0;
+        n = 0;
+    }
+};
+}  // namespace
 
 struct hsp_state {
     int device = 0;
@@ -26,6 +92,9 @@ struct hsp_state {
     hsp_options opt{};
     XLayout x{};
     void* Xbuf = nullptr;
+    int32_t* xexp = nullptr;        // p: column j of Xbuf is stored times 2^-xexp[j]
+    double* xscale = nullptr;       // p: 2^xexp[j]
+    std::vector<double> xscale_h;   // host copy of xscale
     uint8_t* y = nullptr;
     Ctrl* ctrl = nullptr;
     double *beta = nullptr, *lam = nullptr, *nu = nullptr, *tau = nullptr, *xi = nullptr;
@@ -50,8 +119,7 @@ struct hsp_state {
     const hsp_state* owner = nullptr;  // batch chain: X, y, G, Gp belong to this state
     bool in_batch = false;             // owned by an hsp_batch (not destroyed alone)
     bool timing = false;
-    std::vector<hipEvent_t> ev;  // per timed sweep: start, end
-    int64_t timed_sweeps = 0;
+    EventTimer timer;  // timed sweeps
 };
 
 namespace {
@@ -90,6 +158,7 @@ SweepArgs sweep_args(hsp_state* s, uint32_t mode) {
     a.x = s->x;
     a.y = dev_ptr(s->y);
     a.beta32 = dev_ptr(s->beta32);
+    a.xscale = dev_ptr(static_cast<const double*>(s->xscale));
     a.partial = dev_ptr(s->partial);
     a.bsum = dev_ptr(s->bsum);
     a.zgrp_count = dev_ptr(s->zgrp_count);
@@ -183,14 +252,16 @@ void free_state(hsp_state* s) {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     if (s->graph) (void)hipGraphExecDestroy(s->graph);
-    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    s->timer.reset();
     if (s->owner) {  // borrowed from the dataset's first chain
         s->Xbuf = nullptr;
+        s->xexp = nullptr;
+        s->xscale = nullptr;
         s->y = nullptr;
         s->G = nullptr;
         s->Gp = nullptr;
     }
-    void* bufs[] = {s->Xbuf, s->y, s->ctrl, s->beta, s->lam, s->nu, s->tau, s->xi, s->b, s->G, s->Gp,
+    void* bufs[] = {s->Xbuf, s->xexp, s->xscale, s->y, s->ctrl, s->beta, s->lam, s->nu, s->tau, s->xi, s->b, s->G, s->Gp,
                     s->A, s->Linv, s->vec, s->partial, s->beta32, s->zdbg, s->adbg,
                     s->ring_beta, s->ring_tau, s->ring_lam, s->trace, s->bsum,
                     s->zgrp_count, s->dargs, s->dtab, s->tasks, s->task_off, s->ver};
@@ -204,7 +275,7 @@ hsp_status upload_state(hsp_state* s, const double* beta, const double* lam, con
                         double tau, double xi) {
     const uint32_t p = s->x.p;
     std::vector<float> b32(s->x.ld, 0.0f);
-    for (uint32_t j = 0; j < p; ++j) b32[j] = (float)beta[j];
+    for (uint32_t j = 0; j < p; ++j) b32[j] = (float)(beta[j] / s->xscale_h[j]);
     HIP_TRY(hipMemcpy(s->beta, beta, p * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->beta32, b32.data(), s->x.ld * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->lam, lam, p * sizeof(double), hipMemcpyHostToDevice));
@@ -267,18 +338,50 @@ hsp_status create_impl(hsp_state* s, const float* X, const uint8_t* y, int64_t N
     HIP_TRY(hipMemsetAsync(s->ctrl, 0, sizeof(Ctrl), s->stream));
     const hipMemcpyKind kind = s->opt.x_on_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
 
-    // X into the library layout
-    if (xt == HSP_X_F32 && ld == (uint32_t)p) {
-        HIP_TRY(hipMemcpyAsync(s->Xbuf, X, (size_t)N * p * 4, kind, s->stream));
-    } else if (!s->opt.x_on_host) {
-        HIP_TRY(pack_x_launch(X, s->x, s->stream));
-    } else {
+    // X into the library layout, column j scaled by 2^-e_j so that its
+    // largest magnitude lies in (1/2, 1]: the column maxima come first, from
+    // the float32 source on the device (the caller's X, a staging copy of a
+    // host X, or the library buffer itself when the layouts coincide).
+    HIP_TRY(dalloc(&s->xexp, (size_t)p));
+    HIP_TRY(dalloc(&s->xscale, (size_t)p));
+    {
+        const bool inplace = xt == HSP_X_F32 && ld == (uint32_t)p;
         float* stage = nullptr;
-        HIP_TRY(dalloc(&stage, (size_t)N * p));
-        hipError_t e = hipMemcpyAsync(stage, X, (size_t)N * p * 4, kind, s->stream);
-        if (!e) e = pack_x_launch(stage, s->x, s->stream);
+        const float* src = X;
+        if (inplace) {
+            HIP_TRY(hipMemcpyAsync(s->Xbuf, X, (size_t)N * p * 4, kind, s->stream));
+            src = static_cast<const float*>(s->Xbuf);
+        } else if (s->opt.x_on_host) {
+            HIP_TRY(dalloc(&stage, (size_t)N * p));
+            src = stage;
+        }
+        uint32_t* cm = nullptr;
+        hipError_t e = dalloc(&cm, (size_t)p);
+        if (!e && stage) e = hipMemcpyAsync(stage, X, (size_t)N * p * 4, kind, s->stream);
+        if (!e) e = hipMemsetAsync(cm, 0, (size_t)p * 4, s->stream);
+        if (!e) e = colmax_launch(src, (uint32_t)N, (uint32_t)p, cm, s->stream);
+        std::vector<uint32_t> bits(p);
+        if (!e) e = hipMemcpyAsync(bits.data(), cm, (size_t)p * 4, hipMemcpyDeviceToHost, s->stream);
         if (!e) e = hipStreamSynchronize(s->stream);
-        (void)hipFree(stage);
+        std::vector<int32_t> ex(p, 0);
+        s->xscale_h.assign(p, 1.0);
+        for (int64_t j = 0; !e && j < p; ++j) {
+            // a zero or non-finite column keeps scale 1 (non-finite X is rejected below)
+            if (bits[j] == 0 || bits[j] >= 0x7F800000u) continue;
+            float m;
+            std::memcpy(&m, &bits[j], 4);
+            int k = 0;
+            const float f = std::frexp(m, &k);  // m = f 2^k, f in [1/2, 1)
+            ex[j] = f == 0.5f ? k - 1 : k;
+            s->xscale_h[j] = std::ldexp(1.0, ex[j]);
+        }
+        if (!e) e = hipMemcpyAsync(s->xexp, ex.data(), (size_t)p * 4, hipMemcpyHostToDevice, s->stream);
+        if (!e) e = hipMemcpyAsync(s->xscale, s->xscale_h.data(), (size_t)p * 8, hipMemcpyHostToDevice,
+                                   s->stream);
+        if (!e) e = pack_x_launch(src, s->x, s->xexp, s->stream);
+        if (!e) e = hipStreamSynchronize(s->stream);
+        if (cm) (void)hipFree(cm);
+        if (stage) (void)hipFree(stage);
         HIP_TRY(e);
     }
     HIP_TRY(hipMemcpyAsync(s->y, y, (size_t)N, kind, s->stream));
@@ -299,7 +402,7 @@ hsp_status create_impl(hsp_state* s, const float* X, const uint8_t* y, int64_t N
     {
         double* work = nullptr;
         HIP_TRY(dalloc(&work, gram_work_doubles(s->x, s->num_cus)));
-        hipError_t e = gram_launch(s->x, s->G, work, s->num_cus, s->stream);
+        hipError_t e = gram_launch(s->x, s->xexp, s->G, work, s->num_cus, s->stream);
         if (!e && s->Gp) e = pad_gram_launch(s->G, (uint32_t)p, (uint32_t)P, s->Gp, s->stream);
         if (!e) e = hipStreamSynchronize(s->stream);
         (void)hipFree(work);
@@ -316,6 +419,9 @@ hsp_status clone_impl(hsp_state* s, const hsp_state* owner) {
     s->owner = owner;
     s->x = owner->x;
     s->Xbuf = owner->Xbuf;
+    s->xexp = owner->xexp;
+    s->xscale = owner->xscale;
+    s->xscale_h = owner->xscale_h;
     s->y = owner->y;
     s->G = owner->G;
     s->Gp = owner->Gp;
@@ -481,7 +587,7 @@ struct hsp_batch {
     bool own_stream = false;
     hipGraphExec_t graph = nullptr;  // every chain's sweep, one after another
     bool timing = false;
-    std::vector<hipEvent_t> ev;  // per timed batched sweep: start, end
+    EventTimer timer;  // timed batched sweeps
     std::string err;
 };
 
@@ -498,7 +604,7 @@ void free_batch(hsp_batch* b) {
         for (uint32_t* q : pk.sched)
             if (q) (void)hipFree(q);
     }
-    for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+    b->timer.reset();
     for (auto it = b->chains.rbegin(); it != b->chains.rend(); ++it) free_state(*it);  // borrowers first
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
@@ -540,16 +646,21 @@ uint32_t count_tasks(uint32_t nt) {
     return n;
 }
 
-// Split the chains of each storage type into packs that fit the device's
-// resident capacity, and split each pack's blocks among its chains so that
-// the slowest chain of the pack is as fast as the model allows.
+// Split the chains into packs that fit the device's resident capacity, and
+// split each pack's blocks among its chains so that the slowest chain of the
+// pack is as fast as the model allows.  A pack holds chains of one storage
+// type and one z-pass tile height R (rows per wave tile): the pack's kernel
+// is built for its widest rows, and a wider kernel of the same R sums every
+// tile of a narrower chain exactly as that chain's own kernel does (its extra
+// columns are zeros), so a chain draws in a pack what it draws alone.
 hsp_status plan_packs(hsp_batch* b) {
     const int num_cus = b->chains[0]->num_cus;
-    for (int xt = 0; xt < 2; ++xt) {
+    for (int xt = 0; xt < 2; ++xt)
+    for (int R : {8, 4, 2}) {
         std::vector<size_t> ids;
         int chunks = 1;
         for (size_t i = 0; i < b->chains.size(); ++i)
-            if (b->chains[i]->x.xtype == xt) {
+            if (b->chains[i]->x.xtype == xt && rows_for_chunks(b->chains[i]->plan.chunks) == R) {
                 ids.push_back(i);
                 chunks = std::max(chunks, b->chains[i]->plan.chunks);
             }
@@ -759,18 +870,12 @@ hsp_status hsp_batch_sweep(hsp_batch* b, int64_t n) {
         if (e) return batch_fail(b, HSP_EHIP, std::string("batch graph capture: ") + hipGetErrorString(e));
     }
     for (int64_t i = 0; i < n; ++i) {
-        hipEvent_t e2[2] = {nullptr, nullptr};
-        if (b->timing) {
-            for (auto& e : e2)
-                if (hipEventCreate(&e) != hipSuccess) return batch_fail(b, HSP_EHIP, "event creation");
-            b->ev.push_back(e2[0]);
-            b->ev.push_back(e2[1]);
-            if (hipEventRecord(e2[0], b->stream) != hipSuccess) return batch_fail(b, HSP_EHIP, "event record");
-        }
+        if (b->timing && b->timer.begin(b->stream) != hipSuccess)
+            return batch_fail(b, HSP_EHIP, "timing event");
         if (hipGraphLaunch(b->graph, b->stream) != hipSuccess)
             return batch_fail(b, HSP_EHIP, "batch graph launch");
-        if (b->timing && hipEventRecord(e2[1], b->stream) != hipSuccess)
-            return batch_fail(b, HSP_EHIP, "event record");
+        if (b->timing && b->timer.end(b->stream) != hipSuccess)
+            return batch_fail(b, HSP_EHIP, "timing event");
     }
     for (hsp_state* s : b->chains) s->sweeps_done += (uint64_t)n;
     return HSP_OK;
@@ -789,8 +894,7 @@ hsp_status hsp_batch_sync(hsp_batch* b) {
 hsp_status hsp_batch_set_timing(hsp_batch* b, int32_t enable) {
     if (!b) return HSP_EINVAL;
     if (hipStreamSynchronize(b->stream) != hipSuccess) return batch_fail(b, HSP_EHIP, "stream synchronisation");
-    for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
-    b->ev.clear();
+    b->timer.reset();
     b->timing = enable != 0;
     return HSP_OK;
 }
@@ -798,16 +902,10 @@ hsp_status hsp_batch_set_timing(hsp_batch* b, int32_t enable) {
 hsp_status hsp_batch_get_timing(hsp_batch* b, double* ms_per_sweep, int64_t* n) {
     if (!b || !ms_per_sweep) return HSP_EINVAL;
     if (hipStreamSynchronize(b->stream) != hipSuccess) return batch_fail(b, HSP_EHIP, "stream synchronisation");
-    const size_t ns = b->ev.size() / 2;
-    double sum = 0.0;
-    for (size_t i = 0; i < ns; ++i) {
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, b->ev[2 * i], b->ev[2 * i + 1]) != hipSuccess)
-            return batch_fail(b, HSP_EHIP, "event timing");
-        sum += ms;
-    }
-    *ms_per_sweep = ns ? sum / ns : 0.0;
-    if (n) *n = (int64_t)ns;
+    double span = 0.0;
+    int64_t cnt = 0;
+    if (b->timer.result(ms_per_sweep, &span, &cnt) != hipSuccess) return batch_fail(b, HSP_EHIP, "event timing");
+    if (n) *n = cnt;
     return HSP_OK;
 }
 
@@ -832,17 +930,11 @@ hsp_status hsp_sweep(hsp_state* s, int64_t n) {
         if (e) return fail_hip(s, "graph capture", e);
     }
     for (int64_t i = 0; i < n; ++i) {
-        hipEvent_t e2[2] = {nullptr, nullptr};
-        if (s->timing) {
-            for (auto& e : e2) HIP_TRY(hipEventCreate(&e));
-            for (auto& e : e2) s->ev.push_back(e);
-            HIP_TRY(hipEventRecord(e2[0], s->stream));
-        }
+        if (s->timing) HIP_TRY(s->timer.begin(s->stream));
         if (s->graph) HIP_TRY(hipGraphLaunch(s->graph, s->stream));
         else HIP_TRY(enqueue_sweep(s, s->stream));
-        if (s->timing) HIP_TRY(hipEventRecord(e2[1], s->stream));
+        if (s->timing) HIP_TRY(s->timer.end(s->stream));
     }
-    if (s->timing) s->timed_sweeps += n;
     s->sweeps_done += (uint64_t)n;
     return HSP_OK;
 }
@@ -991,9 +1083,7 @@ hsp_status hsp_get_counters(hsp_state* s, uint64_t* clamps, uint32_t* max_attemp
 hsp_status hsp_set_timing(hsp_state* s, int32_t enable) {
     if (!s) return HSP_EINVAL;
     HIP_TRY(hipStreamSynchronize(s->stream));
-    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
-    s->ev.clear();
-    s->timed_sweeps = 0;
+    s->timer.reset();
     s->timing = enable != 0;
     return HSP_OK;
 }
@@ -1001,23 +1091,13 @@ hsp_status hsp_set_timing(hsp_state* s, int32_t enable) {
 hsp_status hsp_get_timing(hsp_state* s, double* zpass_ms, double* sweep_ms, int64_t* n) {
     if (!s) return HSP_EINVAL;
     HIP_TRY(hipStreamSynchronize(s->stream));
-    double sum = 0.0;
-    const size_t ns = s->ev.size() / 2;
-    for (size_t i = 0; i < ns; ++i) {
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, s->ev[2 * i], s->ev[2 * i + 1]));
-        sum += ms;
-    }
-    double total = 0.0;
-    if (ns) {
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, s->ev[0], s->ev[2 * ns - 1]));
-        total = ms;
-    }
+    double mean = 0.0, span = 0.0;
+    int64_t cnt = 0;
+    HIP_TRY(s->timer.result(&mean, &span, &cnt));
     // one kernel per sweep: the z pass and the p-side group share the launch
-    if (zpass_ms) *zpass_ms = ns ? sum / ns : 0.0;
-    if (sweep_ms) *sweep_ms = ns ? total / ns : 0.0;
-    if (n) *n = (int64_t)ns;
+    if (zpass_ms) *zpass_ms = mean;
+    if (sweep_ms) *sweep_ms = span;
+    if (n) *n = cnt;
     return HSP_OK;
 }
 
@@ -1052,6 +1132,48 @@ hsp_status hsp_get_phase_trace(hsp_state* s, uint64_t* out, int64_t* group_block
     if (group_blocks) *group_blocks = s->plan.gp;
     if (slots) *slots = kTraceSlots;
     if (ticks_per_us) *ticks_per_us = (double)s->timeout_ticks / 2e6;
+    return HSP_OK;
+}
+
+namespace {
+// Arguments of hsp_gram as a layout of the Gram kernels, or an error text.
+const char* gram_args(const void* X, int32_t x_type, int64_t N, int64_t p, int64_t ld, const double* G,
+                      XLayout* x) {
+    if (!X || !G) return "X and G must not be NULL";
+    if (x_type != HSP_X_F32 && x_type != HSP_X_BF16) return "x_type must be HSP_X_F32 or HSP_X_BF16";
+    if (N < 1 || p < 1 || ld < p) return "need N >= 1, p >= 1 and ld >= p";
+    if (N >= (int64_t(1) << 32) || ld >= (int64_t(1) << 32)) return "N and ld must be below 2^32";
+    x->X = dev_ptr(X);
+    x->xtype = x_type;
+    x->N = (uint32_t)N;
+    x->p = (uint32_t)p;
+    x->ld = (uint32_t)ld;
+    return nullptr;
+}
+
+hsp_status gram_device(int* num_cus) {
+    hsp_state* s = nullptr;  // HIP_TRY reports through the creation error text
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(num_cus, hipDeviceAttributeMultiprocessorCount, dev));
+    return HSP_OK;
+}
+}  // namespace
+
+hsp_status hsp_gram(const void* X, int32_t x_type, int64_t N, int64_t p, int64_t ld, double* G,
+                    void* hip_stream) {
+    hsp_state* s = nullptr;
+    XLayout x{};
+    if (const char* msg = gram_args(X, x_type, N, p, ld, G, &x)) return fail(nullptr, HSP_EINVAL, msg);
+    int num_cus = 0;
+    if (hsp_status st = gram_device(&num_cus)) return st;
+    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    double* work = nullptr;
+    HIP_TRY(dalloc(&work, gram_work_doubles(x, num_cus)));
+    hipError_t e = gram_launch(x, nullptr, G, work, num_cus, st);
+    if (!e) e = hipStreamSynchronize(st);
+    (void)hipFree(work);
+    HIP_TRY(e);
     return HSP_OK;
 }
 

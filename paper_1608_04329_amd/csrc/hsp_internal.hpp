@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <vector>
 
 namespace hsp {
@@ -98,7 +99,12 @@ enum : uint32_t {
 };
 
 // Layout of X in device memory: row-major, leading dimension ld elements,
-// ld a multiple of 16 bytes, padding columns zero.
+// ld a multiple of 16 bytes, padding columns zero.  Column j is stored
+// multiplied by 2^-e_j, e_j chosen so that its largest magnitude lies in
+// (1/2, 1]: the library's X is X D with D = diag(2^-e_j), an exact scaling.
+// The z pass then runs on X D and beta D^-1 (the same products x_ij beta_j,
+// bit for bit) and its X^T z comes out as D X^T z, so the fixed grid on
+// which tile sums are rounded is 2^-24 of each column's own scale.
 struct XLayout {
     HSP_GLOBAL const void* X;
     int xtype;  // 0 float32, 1 bfloat16
@@ -111,7 +117,8 @@ struct XLayout {
 struct SweepArgs {
     XLayout x;
     HSP_GLOBAL const uint8_t* y;
-    HSP_GLOBAL float* beta32;      // ld floats (padding zero): beta for the z pass
+    HSP_GLOBAL float* beta32;      // ld floats (padding zero): beta_j 2^-e_j for the z pass
+    HSP_GLOBAL const double* xscale;  // p: 2^e_j, the scale of column j of the stored X
     HSP_GLOBAL double* partial;    // gz x ld: per-block float64 partials of X^T z
     HSP_GLOBAL double* bsum;       // ld: X^T z accumulated by the z groups (zero between launches)
     HSP_GLOBAL uint32_t* zgrp_count;  // zgroups arrival counters (zero between launches)
@@ -199,10 +206,24 @@ int pack_capacity(int xtype, int chunks, int num_cus);
 hipError_t pack_launch(int xtype, int chunks, const SweepArgs* const* table, const uint16_t* chain_of_block,
                        uint32_t blocks, hipStream_t st);
 
-// G = X^T X (p x p float64, leading dimension p); work must hold
-// gram_work_doubles(x) doubles.
+// G = X^T X (p x p float64, leading dimension p) of the stored X, unscaled
+// with the column exponents e (null: none).  The rows are cut into nsplit
+// splits of rows_per_split rows and the upper triangle of G into npairs
+// 64 x 64 tiles; every (split, tile) partial is summed in split order.
+struct GramGeometry {
+    uint32_t nt, npairs, nsplit, rows_per_split;
+};
+GramGeometry gram_geometry(const XLayout& x, int num_cus);
+// Doubles of workspace that hold every partial tile at once.
 size_t gram_work_doubles(const XLayout& x, int num_cus);
-hipError_t gram_launch(const XLayout& x, double* G, double* work, int num_cus, hipStream_t st);
+// work must hold gram_work_doubles(x) doubles.
+hipError_t gram_launch(const XLayout& x, const int32_t* e, double* G, double* work, int num_cus,
+                       hipStream_t st);
+// The same G (bit for bit) with a workspace of work_doubles doubles: the
+// tiles are processed in chunks whose partials fit it (at least one tile's
+// nsplit partials, else hipErrorInvalidValue).
+hipError_t gram_launch_chunked(const XLayout& x, const int32_t* e, double* G, double* work,
+                               size_t work_doubles, int num_cus, hipStream_t st);
 // Gp (P x P) = G with an identity block beyond p, zeros elsewhere.
 hipError_t pad_gram_launch(const double* G, uint32_t p, uint32_t P, double* Gp, hipStream_t st);
 
@@ -210,9 +231,16 @@ hipError_t pad_gram_launch(const double* G, uint32_t p, uint32_t P, double* Gp, 
 // not finite.
 hipError_t validate_launch(const XLayout& x, const uint8_t* y, Ctrl* ctrl, hipStream_t st);
 
+// Largest |x_ij| of every column of a float32 N x p matrix (leading dimension
+// p): colmax_bits[j] receives the float bits of max_i |x_ij| (atomic maximum
+// on the bit pattern; start from zeros).
+hipError_t colmax_launch(const float* src, uint32_t N, uint32_t p, uint32_t* colmax_bits,
+                         hipStream_t st);
+
 // Copy / convert a float32 N x p matrix (leading dimension p) into the padded
-// library layout.
-hipError_t pack_x_launch(const float* src, const XLayout& dst, hipStream_t st);
+// library layout, column j multiplied by 2^-e[j] (exact).  src may be the
+// destination itself when the layouts coincide (float32, ld = p).
+hipError_t pack_x_launch(const float* src, const XLayout& dst, const int32_t* e, hipStream_t st);
 
 // Stream `bytes` of x with plain 16-byte loads only (the read ceiling).
 hipError_t stream_read_launch(const void* x, size_t bytes, int num_cus, float* sink, hipStream_t st);

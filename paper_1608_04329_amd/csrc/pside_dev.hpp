@@ -361,9 +361,10 @@ __device__ void small_path(Args& a, Group& g, uint32_t k, double* lds) {
             wait_count(&a.ctrl->z_count, g.zbase + a.zgroups, a.ctrl, a.timeout_ticks, 64);
         }
         __syncthreads();
-        // b as the z groups accumulated it; wave 0 takes it from LDS below
+        // b as the z groups accumulated it (in the units of the stored X,
+        // unscaled exactly); wave 0 takes it from LDS below
         for (uint32_t j = threadIdx.x; j < p; j += kThreads) {
-            const double s = ldc(&a.bsum[j]);
+            const double s = ldc(&a.bsum[j]) * a.xscale[j];
             a.b[j] = s;
             lds[kSmallBOff + j] = s;
         }
@@ -396,7 +397,7 @@ __device__ void small_path(Args& a, Group& g, uint32_t k, double* lds) {
             if (j < p) {
                 const double bj = w[q] + v[q];
                 a.beta[j] = bj;
-                a.beta32[j] = (float)bj;
+                a.beta32[j] = (float)(bj / a.xscale[j]);
                 if (!isfinite(bj)) nonfinite = true;
                 if (keep) a.ring_beta[(size_t)slot * p + j] = bj;
             }
@@ -902,7 +903,7 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
         double s = 0.0;
         if (j < p) {
             if (a.mode & kModeZ) {
-                s = ldc(&a.bsum[j]);
+                s = ldc(&a.bsum[j]) * a.xscale[j];  // unscaled exactly
                 if (rank == 0) a.b[j] = s;
             } else {
                 s = a.b[j];
@@ -995,7 +996,7 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
                     double bi = 0.0;
                     for (int q = 0; q < 16; ++q) bi += red[q * 17 + tc];
                     a.beta[col] = bi;
-                    a.beta32[col] = (float)bi;
+                    a.beta32[col] = (float)(bi / a.xscale[col]);
                     if (!isfinite(bi)) nonfinite = true;
                     if (keep) {
                         a.ring_beta[(size_t)slot * p + col] = bi;

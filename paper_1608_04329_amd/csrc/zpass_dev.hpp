@@ -58,7 +58,10 @@ __device__ __forceinline__ uint32_t word_of(const uint4& v, int i) {
 // A tile's float32 sum of x_ij z_i, rounded to a multiple of 2^-24 (for
 // |v| < 2^27).  Sums of such values below 2^29 in magnitude are exact in
 // float64, so X^T z does not depend on which block summed which rows or in
-// what order: the dynamically dealt tiles keep b bitwise reproducible.
+// what order: the dynamically dealt tiles keep b bitwise reproducible.  The
+// stored X has every column scaled into (-1, 1] by a power of two, so the
+// grid is 2^-24 of the column's own scale, and the sums stay below 2^29 while
+// sum_i |z_i| does.
 __device__ __forceinline__ double on_grid(double v) {
     constexpr double kC = 0x1.8p28;  // 1.5 * 2^28: its float64 spacing is 2^-24
     return (v + kC) - kC;

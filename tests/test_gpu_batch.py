@@ -96,6 +96,29 @@ def test_batch_chain_equals_lone_chain(env):
             i += 1
 
 
+def test_batch_mixed_tile_heights_equal_lone_chains(env):
+    """Float32 chains with p <= 1024 (8-row z tiles) and p > 1024 (4-row
+    tiles) in one batch: each pack keeps one tile height, so every chain
+    still draws bitwise what it draws alone."""
+    torch, hsp = env
+    sets = [((2003, 1000, 66), "f32", 1), ((2003, 1100, 67), "f32", 1), ((1500, 300, 68), "f32", 1),
+            ((1500, 2100, 69), "bf16", 1), ((1800, 700, 70), "bf16", 1)]
+    ds, b = make_batch(env, sets, seed=6, chain_id=2)
+    b.sweep(3)
+    b.sync()
+    batch = [b.chain(i).draws() for i in range(len(b))]
+    b.close()
+    for i, (d, xt, _) in enumerate(ds):
+        s = hsp.Sampler(torch.from_numpy(d.X).cuda(), torch.from_numpy(d.y).cuda(), seed=6,
+                        chain_id=2 + i, x_type=xt)
+        s.sweep(3)
+        bl, tl, nl = s.draws()
+        s.close()
+        bb, tb, nb = batch[i]
+        assert nb == nl == 3
+        assert np.array_equal(bb, bl) and np.array_equal(tb, tl), (i, d.p, xt)
+
+
 def test_batch_is_reproducible(env):
     outs = []
     for _ in range(2):

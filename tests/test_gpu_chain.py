@@ -4,9 +4,17 @@
   agree on the posterior mean and variance of every beta_j within
   4 sqrt(MCSE_gpu^2 + MCSE_oracle^2) (batch means, 20% burn-in), and the
   sign of each nonzero beta_true must be recovered (Section 6.1).
-* Full size (N = 1,000,000, p = 1000, float32 X; the benchmark's launch): one
-  z step and X^T z compared with the oracle on every row, G on sampled
-  entries, and 50 whole sweeps checked for the sign invariant and finiteness.
+* Full size (N = 1,000,000, p = 1000, float32 X and bfloat16 X; the
+  benchmark's launches): one z step and X^T z compared with the oracle on
+  every row, G on sampled entries, and whole sweeps checked for the sign
+  invariant and finiteness.
+
+X^T z at full size is held to the oracle in two ways that hold whether or not
+some row took another proposal than the oracle (a float32 vs float64
+decision at a threshold): the GPU's b against the oracle's X^T z of the
+GPU's own z (the product of X with the z the kernel drew), and against the
+oracle's b with the flipped rows' difference |x_ij| |z_i - z_i'| added to
+the bar.
 """
 import math
 
@@ -83,6 +91,26 @@ def test_long_chain_moments_agree_with_oracle(env, orc, which):
     assert np.all((np.sign(hi) == np.sign(d.beta_true[nz]))[big])
 
 
+def check_full_size_z_step(orc, hsp, s, Xo, Xf, y, beta, seed, k):
+    """One z step at full size against the oracle, every row."""
+    s.step(hsp.HSP_STEP_Z)
+    z, att, b = s.debug()
+    zo, ao, bo = orc.z_step(Xo, y, beta, seed, k)
+    assert np.all(z * (2.0 * y - 1.0) > 0)
+    flips = ((att & ~(1 << 30)) != ao) | (((att & (1 << 30)) != 0) != (bo == 1))
+    assert flips.sum() <= int(1e-5 * y.size)
+    ok = ~flips
+    assert np.max(np.abs(z[ok] - zo[ok]) / z_scale(Xf[ok], beta)) < 1e-5
+    # X^T z of the kernel's own z, and the oracle's b with the flipped rows' share
+    scale = b_scale(Xf, zo)
+    assert np.max(np.abs(b - orc.xtz(Xo, z.astype(np.float64))) / b_scale(Xf, z)) < 1e-5
+    dz = np.abs(z.astype(np.float64) - zo)
+    dz[ok] = 0.0
+    slack = np.abs(Xf[flips].astype(np.float64)).T @ dz[flips] if flips.any() else 0.0
+    assert np.all(np.abs(b - orc.xtz(Xo, zo)) <= 1e-5 * scale + slack)
+    return flips.sum()
+
+
 def test_full_size_workload(env, orc):
     torch, hsp = env
     d = synth.config3()
@@ -99,16 +127,7 @@ def test_full_size_workload(env, orc):
     beta[d.beta_true != 0] = d.beta_true[d.beta_true != 0]
     beta += rng.normal(0, 0.01, d.p)
     s.set_state(beta, np.ones(d.p), np.ones(d.p), 1.0, 1.0, 30)
-    s.step(hsp.HSP_STEP_Z)
-    z, att, b = s.debug()
-    zo, ao, bo = orc.z_step(d.X, d.y, beta, 1, 31)
-    assert np.all(z * (2.0 * d.y - 1.0) > 0)
-    flips = ((att & ~(1 << 30)) != ao) | (((att & (1 << 30)) != 0) != (bo == 1))
-    assert flips.sum() <= int(1e-5 * d.N)
-    ok = ~flips
-    assert np.max(np.abs(z[ok] - zo[ok]) / z_scale(d.X[ok], beta)) < 1e-5
-    if flips.sum() == 0:
-        assert np.max(np.abs(b - orc.xtz(d.X, zo)) / b_scale(d.X, zo)) < 1e-5
+    check_full_size_z_step(orc, hsp, s, d.X, d.X, d.y, beta, 1, 31)
     # 50 whole sweeps from the cold start, as timed by the benchmark
     s.set_state(np.zeros(d.p), np.ones(d.p), np.ones(d.p), 1.0, 1.0, 0)
     s.sweep(50)
@@ -119,6 +138,37 @@ def test_full_size_workload(env, orc):
     clamps, maxatt = s.counters()
     assert clamps == 0 and maxatt < 64
     # the chain has moved towards the truth on the nonzero coefficients
+    nz = np.flatnonzero(d.beta_true)
+    assert np.corrcoef(betas[-1][nz], d.beta_true[nz])[0, 1] > 0.9
+    s.close()
+
+
+def test_full_size_bf16_workload(env, orc):
+    """The bfloat16 form at its throughput shape (N = 1e6, p = 1000, 2 GB):
+    matched-design parity of the z step and X^T z on every row, G on sampled
+    entries, and whole sweeps."""
+    torch, hsp = env
+    d = synth.config3()
+    bits = synth.bf16_bits(d.X).reshape(d.X.shape)
+    Xf = synth.bf16_to_f32(bits).reshape(d.X.shape)
+    s = hsp.Sampler(d.X, d.y, seed=2, x_type="bf16", debug_store_z=True, max_draws=64)
+    rng = np.random.default_rng(6)
+    G = s.gram()
+    for _ in range(16):
+        j, k = rng.integers(0, d.p, 2)
+        ref = orc.gram_entry(bits, int(j), int(k))
+        assert abs(G[j, k] - ref) <= 1e-12 * math.sqrt(G[j, j] * G[k, k])
+    beta = np.zeros(d.p)
+    beta[d.beta_true != 0] = d.beta_true[d.beta_true != 0]
+    beta += rng.normal(0, 0.01, d.p)
+    s.set_state(beta, np.ones(d.p), np.ones(d.p), 1.0, 1.0, 40)
+    check_full_size_z_step(orc, hsp, s, bits, Xf, d.y, beta, 2, 41)
+    s.set_state(np.zeros(d.p), np.ones(d.p), np.ones(d.p), 1.0, 1.0, 0)
+    s.sweep(30)
+    z, att, b = s.debug()
+    assert np.all(z * (2.0 * d.y - 1.0) > 0)
+    betas, taus, n = s.draws()
+    assert n == 30 and np.all(np.isfinite(betas)) and np.all(taus > 0)
     nz = np.flatnonzero(d.beta_true)
     assert np.corrcoef(betas[-1][nz], d.beta_true[nz])[0, 1] > 0.9
     s.close()

@@ -24,14 +24,16 @@ def make(env, d, seed, **kw):
     return hsp.Sampler(torch.from_numpy(d.X).cuda(), torch.from_numpy(d.y).cuda(), seed=seed, **kw)
 
 
-@pytest.mark.parametrize("N,p", [(5003, 10), (4099, 100), (2051, 257), (2003, 1000)])
+# Beyond p = 2048 the bfloat16 z pass holds 4-row tiles.
+@pytest.mark.parametrize("N,p", [(5003, 10), (4099, 100), (2051, 257), (2003, 1000), (1501, 2049),
+                                 (1000, 4096)])
 def test_bf16_matched_design(env, orc, N, p):
     torch, hsp = env
     d = dataset(N, p, 300 + p)
     bits = synth.bf16_bits(d.X).reshape(d.X.shape)
     s = make(env, d, 5, x_type="bf16", debug_store_z=True)
     G = s.gram()
-    Gm = orc.gram(bits)
+    Gm = orc.gram(bits) if p <= 1000 else orc.gram_fast(bits)
     scale = np.sqrt(np.outer(np.diag(Gm), np.diag(Gm)))
     assert np.max(np.abs(G - Gm) / scale) < 1e-12
     st = random_state(p, 310 + p, beta_scale=1.5 / np.sqrt(p))
@@ -139,10 +141,21 @@ def test_invalid_inputs_rejected(env):
         hsp.Sampler(X, d.y)
     assert e.value.code == hsp.HSP_EINVAL
     X = d.X.copy()
-    X[10, 2] = 3.4e38  # finite in float32, infinite after bfloat16 rounding
+    X[10, 2] = np.inf
     with pytest.raises(hsp.HspError) as e:
         hsp.Sampler(X, d.y, x_type="bf16")
     assert e.value.code == hsp.HSP_EINVAL
+    # near the float32 limit: bfloat16 rounding would overflow it, but the
+    # library stores every column scaled into (-1, 1] first, so it is valid
+    X = d.X.copy()
+    X[10, 2] = 3.4e38
+    s = hsp.Sampler(X, d.y, x_type="bf16")
+    G = s.gram()
+    big = float(synth.bf16_to_f32(synth.bf16_bits(np.array([3.4e38 * 2.0**-128], np.float32))))
+    assert np.isfinite(G).all() and G[2, 2] >= (big * 2.0**128) ** 2
+    s.sweep(2)
+    assert np.all(np.isfinite(s.state()["beta"]))
+    s.close()
     s = hsp.Sampler(d.X, d.y)  # host input path
     with pytest.raises(hsp.HspError) as e:
         s.set_state(np.zeros(12), -np.ones(12), np.ones(12), 1.0, 1.0, 0)

@@ -19,9 +19,16 @@ from gpu_util import b_scale, dataset, need_gpu, random_state, z_scale
 pytestmark = pytest.mark.gpu
 
 # p = 16 is the largest p of the one-block p-side path, p = 17 the smallest of
-# the tiled one (a single 64-wide tile).
+# the tiled one (a single 64-wide tile).  Beyond p = 1024 (float32) the z pass
+# holds 4-row tiles, beyond p = 1792 2-row tiles; p = 4096 is the largest p
+# (64 x 64 tiles of the factorisation).
 SHAPES = [(5003, 2), (5003, 10), (4001, 16), (4001, 17), (4099, 100), (3001, 130), (2051, 257),
-          (2003, 1000)]
+          (2003, 1000), (2003, 1025), (1501, 2049), (1000, 4096)]
+
+
+def gram_of(orc, X):
+    """The oracle's G; for large p the same definition by a library matmul."""
+    return orc.gram(X) if X.shape[1] <= 1000 else orc.gram_fast(X)
 
 
 @pytest.fixture(scope="module")
@@ -52,7 +59,7 @@ def test_gram(env, orc, N, p):
     d = dataset(N, p, 10 + p)
     s = make(env, d, 1)
     G = s.gram()
-    Go = orc.gram(d.X)
+    Go = gram_of(orc, d.X)
     scale = np.sqrt(np.outer(np.diag(Go), np.diag(Go)))
     assert np.max(np.abs(G - Go) / scale) < 1e-12
     assert np.array_equal(G, G.T)
@@ -126,7 +133,7 @@ def test_beta_step(env, orc, N, p):
     s.set_state(st["beta"], st["lam_m2"], st["nu_m1"], st["tau_m2"], st["xi_m1"], k0)
     s.step(hsp.HSP_STEP_Z | hsp.HSP_STEP_BETA)
     beta_gpu = s.state()["beta"]
-    G = orc.gram(d.X)
+    G = gram_of(orc, d.X)
     zo, _, _ = orc.z_step(d.X, d.y, st["beta"], 13, k0 + 1)
     bo = orc.xtz(d.X, zo)
     beta_o, mean_o, noise_o, rc = orc.beta_step(G, st["lam_m2"], st["tau_m2"], bo, 13, k0 + 1)

@@ -113,3 +113,14 @@ def test_bf16_input_is_widened_exactly(orc):
     np.testing.assert_allclose(orc.gram(bits), Xr.T @ Xr, rtol=1e-12, atol=1e-12)
     # bf16 rounding error is at most half an ulp of 8 significant bits
     assert np.all(np.abs(Xr - X) <= np.abs(X) * 2.0**-8 + 1e-30)
+
+
+def test_gram_fast_is_the_same_sum(orc):
+    rng = np.random.default_rng(10)
+    X = rng.standard_normal((700, 37)).astype(np.float32)
+    X[:, 3] *= 2.0**-20
+    X[:, 5] *= 2.0**15
+    for Xa in (X, synth.bf16_bits(X).reshape(X.shape)):
+        G, Gf = orc.gram(Xa), orc.gram_fast(Xa)
+        scale = np.sqrt(np.outer(np.diag(G), np.diag(G)))
+        assert np.max(np.abs(G - Gf) / scale) < 1e-13
