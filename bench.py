@@ -1,26 +1,40 @@
 """Benchmark: Gibbs sweeps per second of the Horseshoe Probit sampler on one
-MI355X, at N = 1,000,000 rows and p = 1000 predictors (X float32, 4 GB).
+MI355X, at N = 1,000,000 rows and p = 1000 predictors.
 
 One step = one full Gibbs sweep (z | beta over all rows fused with X^T z;
 lambda, tau; the float64 Cholesky draw of beta; nu, xi; the draw record).
 Inputs are seeded synthetic data (the paper's Section 6.1 design with an
 intercept and 10 nonzero coefficients) resident in HBM before timing starts.
 
-Prints one JSON line.  Also reports:
+Prints one JSON line.  `value` is the float32-X sweep rate (X is 4.0 GB); the
+line also carries
   roofline      the sweep kernel (one fused launch per sweep; its z pass is the
                 N x p stream): algorithmic bytes per launch (N p 4 + N) over
                 its mean duration from HIP events on the library's stream,
                 against the 8 TB/s HBM peak; traffic = hardware-counted HBM
-                bytes per launch when the stored counter reading matches the
-                current kernel sources
+                bytes per launch while the stored counter reading matches the
+                current kernel sources (else null)
+  bf16          the same workload with X stored in bfloat16 (2.0 GB): its own
+                sweep rate and roofline (N p 2 + N bytes per launch)
+  batch         the batched form: 64 uneven float32 datasets (one chain each)
+                plus 16 chains sharing the N = 1e6, p = 1000 bfloat16 design,
+                one graph replay per batched sweep: chain-sweeps/s batched and
+                the same chains swept one at a time, with the roofline of the
+                whole batched sweep (one read of every distinct design)
+  rare_event    the stand-in for the data of Section 6.2 (N = 1,295,848,
+                p = 141, mean outcome 0.0048): 10,000 sweeps (2,500 burn-in) as
+                the paper ran, with the lag-1 autocorrelation and effective
+                sample size of the coefficients and the truncated-normal
+                branch mix
   read_ceiling  a plain streaming read of the same X (16-byte non-temporal
                 loads, nothing else) on this GPU: what the z pass could reach
   cpu_baseline  the float64 oracle timed on this host on a bounded sample of
-                the same workload (whole sweeps, one thread)
+                the same workload (whole sweeps), all cores and one thread
 """
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -29,6 +43,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gibbs sweeps/sec and HBM GB/s at N=1e6,p=1000; chain-sweeps/sec batched vs plain"
 HBM_PEAK_GBPS = 8000.0
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
 def parse():
@@ -38,14 +53,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--N", type=int, default=1_000_000)
     ap.add_argument("--p", type=int, default=1000)
-    ap.add_argument("--x-type", default="f32", choices=["f32", "bf16"])
+    ap.add_argument("--only", choices=["f32", "bf16", "batch", "rare"], default=None,
+                    help="run one form only and print its own line (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "sweep_kernel_traffic.json"))
-    ap.add_argument("--batch", action="store_true",
-                    help="the batched form instead: 64 uneven float32 datasets (one chain each) "
-                         "and 16 chains sharing the N=1e6, p=1000 design in bfloat16; reports "
-                         "chain-sweeps/s batched and plain")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--traffic-json", default=TRAFFIC_JSON)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device twice (a plain copy kernel of known "
                          "size, to scale hardware byte counters)")
@@ -70,8 +82,49 @@ def kernel_fingerprint():
     return h.hexdigest()[:16]
 
 
+def stored_traffic(path, workload):
+    """Counted HBM bytes per launch (or per batched sweep) for this workload,
+    if they were taken at the current kernel sources."""
+    try:
+        with open(path) as f:
+            t = json.load(f).get(workload)
+    except (OSError, ValueError):
+        return None
+    if not t or t.get("kernel_fingerprint") != kernel_fingerprint():
+        return None
+    return t.get("bytes")
+
+
+def roofline(bytes_per_launch, ms, traffic):
+    achieved = bytes_per_launch / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic}
+
+
+def host_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    ram = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    ram = round(int(line.split()[1]) / 2**20, 1)
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count(), ram
+
+
 def cpu_baseline(d, seconds):
-    """Whole oracle sweeps on the same data until `seconds` have elapsed."""
+    """Whole oracle sweeps on the same data, on all host cores and on one."""
     import numpy as np
     from oracle import oracle as orc
     # one-time Gram in float64 (untimed, like the GPU's creation step)
@@ -80,36 +133,165 @@ def cpu_baseline(d, seconds):
     for r in range(0, d.N, step):
         xb = d.X[r:r + step].astype(np.float64)
         G += xb.T @ xb
-    ch = orc.Chain(d.p)
-    n = 0
+
+    def time_sweeps(threads, budget):
+        orc.set_threads(threads)
+        ch = orc.Chain(d.p)
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            ch.sweep_once(d.X, d.y, G, seed=1)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= budget or n >= 200:
+                return n, el
+
+    model, nproc, ram = host_info()
+    threads = max(1, min(nproc or 1, orc.max_threads()))
+    na, ea = time_sweeps(threads, seconds / 2)
+    n1, e1 = time_sweeps(1, seconds / 2)
+    orc.set_threads(threads)
+    return {"value": round(na / ea, 4), "unit": "sweeps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{na} whole float64 oracle sweeps of the same N={d.N}, p={d.p} float32 workload "
+                      f"from the cold start on {threads} threads (OpenMP over rows; the p-side is "
+                      f"serial), {ea:.1f} s; Gram formed beforehand (untimed)",
+            "single_thread": {"value": round(n1 / e1, 4), "cores": 1,
+                              "sample": f"{n1} sweeps on one thread, {e1:.1f} s"},
+            "cpu_model": model, "nproc": nproc, "ram_gb": ram}
+
+
+def run_single(a, d, x_type, traffic_path):
+    """One chain on design d with X stored as x_type: sweeps/s and the roofline
+    of the sweep kernel."""
+    import torch
+
+    from paper_1608_04329_amd import hsp
     t0 = time.perf_counter()
-    while True:
-        ch.sweep_once(d.X, d.y, G, seed=1)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or n >= 50:
-            break
-    return {"value": n / el, "unit": "sweeps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} whole float64 oracle sweeps of the same N={d.N}, p={d.p} workload "
-                      f"from the cold start, single thread, {el:.1f} s; Gram formed beforehand "
-                      f"(untimed)"}
+    s = hsp.Sampler(d.X, d.y, seed=1, x_type=x_type, max_draws=max(64, a.steps + a.warmup))
+    print(f"[bench] {x_type}: sampler created (X copied, Gram formed) in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    s.sweep(a.warmup)
+    s.sync()
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.sweep(a.steps)
+    s.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms, sweep_ms, _ = s.timing()
+    clamps, maxatt = s.counters()
+    s.set_timing(False)
+    ceil_ms, ceil_bytes = hsp.hsp_read_ceiling(s.h, 10)
+    s.close()
+    esz = 4 if x_type == "f32" else 2
+    nbytes = d.N * d.p * esz + d.N  # X once, y once
+    workload = f"horseshoe_probit_gibbs_N{d.N}_p{d.p}_x{x_type}"
+    print(f"[bench] {x_type}: {a.steps} sweeps in {elapsed:.3f}s; sweep kernel {kernel_ms:.4f} ms per "
+          f"launch (events)", file=sys.stderr, flush=True)
+    return {
+        "workload": workload,
+        "value": round(a.steps / elapsed, 3),
+        "unit": "sweeps/s",
+        "ms_per_step": round(1e3 * elapsed / a.steps, 5),
+        "kernel_ms": round(kernel_ms, 5),
+        "sweep_ms_events": round(sweep_ms, 5),
+        "hbm_gbps": round(nbytes / (elapsed / a.steps) / 1e9, 1),
+        "algorithmic_bytes_per_launch": nbytes,
+        "read_ceiling": {"gbps": round(ceil_bytes / (ceil_ms * 1e-3) / 1e9, 1),
+                         "ms_per_pass": round(ceil_ms, 5),
+                         "kernel": "plain 16-byte non-temporal streaming read of the same X"},
+        "max_tn_proposals": int(maxatt),
+        "lambda_clamps": int(clamps),
+        "roofline": roofline(nbytes, kernel_ms, stored_traffic(traffic_path, workload)),
+    }
 
 
-def run_batch(a):
-    """Chain-sweeps/s of the batched form against the same chains swept one by one."""
+def ess_and_acf(x):
+    """Lag-1 autocorrelation and effective sample size of each column of x
+    (draws x coefficients): ESS = n / (1 + 2 sum_k rho_k), the sum cut by
+    Geyer's initial monotone sequence of paired autocorrelations."""
+    import numpy as np
+    n = x.shape[0]
+    xc = x - x.mean(0)
+    f = np.fft.rfft(xc, n=2 * n, axis=0)
+    acov = np.fft.irfft(f * np.conj(f), axis=0)[:n] / n
+    rho = acov / np.maximum(acov[0], 1e-300)
+    ess = np.empty(x.shape[1])
+    for j in range(x.shape[1]):
+        r = rho[:, j]
+        pairs = r[0:n - 1:2] + r[1:n:2]
+        m = np.argmax(pairs <= 0) if np.any(pairs <= 0) else pairs.size
+        g = np.minimum.accumulate(pairs[:m]) if m else np.zeros(0)
+        ess[j] = n / max(1e-12, -1.0 + 2.0 * g.sum())
+    return rho[1], ess
+
+
+def run_rare(a, sweeps=10_000, burn=2_500):
+    """The rare-event stand-in for the data of Section 6.2 (N = 1,295,848,
+    p = 141, mean outcome 0.0048): the paper's run length, mixing reported."""
     import numpy as np
     import torch
 
     import synth
     from paper_1608_04329_amd import hsp
-
-    torch.cuda.set_device(0)
     t0 = time.perf_counter()
+    d = synth.rare_event()
+    print(f"[bench] rare-event data generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    s = hsp.Sampler(d.X, d.y, seed=1, max_draws=sweeps, debug_store_z=True)
+    s.sweep(2)
+    s.sync()
+    s.set_state(np.zeros(d.p), np.ones(d.p), np.ones(d.p), 1.0, 1.0, 0)
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.sweep(sweeps)
+    s.sync()
+    elapsed = time.perf_counter() - t0
+    kernel_ms, _, _ = s.timing()
+    s.set_timing(False)
+    betas, taus, _ = s.draws()
+    _, att, _ = s.debug()
+    s.close()
+    gauss = (att & (1 << 30)) != 0
+    rho1, ess = ess_and_acf(betas[burn:])
+    nbytes = d.N * d.p * 4 + d.N
+    return {
+        "workload": f"horseshoe_probit_rare_event_N{d.N}_p{d.p}_ybar{d.y.mean():.4f}_xf32",
+        "value": round(sweeps / elapsed, 2), "unit": "sweeps/s",
+        "sweeps": sweeps, "burn_in": burn, "seconds_for_run": round(elapsed, 3),
+        "kernel_ms": round(kernel_ms, 5),
+        "roofline": roofline(nbytes, kernel_ms, None),
+        "acf_lag1": {"min": round(float(rho1.min()), 4), "median": round(float(np.median(rho1)), 4),
+                     "max": round(float(rho1.max()), 4), "intercept": round(float(rho1[0]), 4)},
+        "ess": {"min": round(float(ess.min()), 1), "median": round(float(np.median(ess)), 1),
+                "intercept": round(float(ess[0]), 1)},
+        "tn_gauss_branch_fraction": round(float(gauss.mean()), 5),
+        "intercept_posterior_mean": round(float(betas[burn:, 0].mean()), 4),
+        "intercept_true": round(float(d.beta_true[0]), 4),
+    }
+
+
+def batch_data(big=None):
+    """The 64 uneven datasets and the shared N = 1e6, p = 1000 design (big, if
+    already generated: the same seeded design as the single-chain workload)."""
+    import synth
     shapes = synth.batch_shapes(64, seed=1000)
     ds = [synth.batch_dataset(k, N, p) for k, (N, p) in enumerate(shapes)]
-    beta_true, _ = synth.sparse_beta(1000, 10, 13)
-    big = synth.probit_design(1_000_000, 1000, beta_true, 13, True, "n1000000_p1000")
-    print(f"[bench] batch data generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    if big is None:
+        beta_true, _ = synth.sparse_beta(1000, 10, 13)
+        big = synth.probit_design(1_000_000, 1000, beta_true, 13, True, "n1000000_p1000")
+    return ds, big
+
+
+def run_batch(a, traffic_path, data=None):
+    """Chain-sweeps/s of the batched form against the same chains swept one by one."""
+    import torch
+
+    from paper_1608_04329_amd import hsp
+    t0 = time.perf_counter()
+    ds, big = data if data is not None else batch_data()
+    print(f"[bench] batch data ready in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     datasets = [(torch.from_numpy(d.X).cuda(), torch.from_numpy(d.y).cuda(), "f32") for d in ds]
     datasets.append((torch.from_numpy(big.X).cuda(), torch.from_numpy(big.y).cuda(), "bf16"))
     counts = [1] * len(ds) + [16]
@@ -128,7 +310,7 @@ def run_batch(a):
     ms_ev, _ = b.timing()
     b.set_timing(False)
     batched = nchains * a.steps / elapsed
-    print(f"[bench] batched: {a.steps} sweeps of {nchains} chains in {elapsed:.3f}s "
+    print(f"[bench] batch: {a.steps} sweeps of {nchains} chains in {elapsed:.3f}s "
           f"({ms_ev:.3f} ms per batched sweep by events)", file=sys.stderr, flush=True)
     # plain: every chain swept on its own, one after another
     t0 = time.perf_counter()
@@ -138,21 +320,22 @@ def run_batch(a):
         c.sync()
     elapsed_plain = time.perf_counter() - t0
     plain = nchains * a.steps / elapsed_plain
-    out = {
-        "metric": "chain-sweeps/sec, batched vs plain",
+    b.close()
+    # one read of every distinct design (and its y) per batched sweep
+    nbytes = sum(d.N * d.p * 4 + d.N for d in ds) + big.N * big.p * 2 + big.N
+    workload = "horseshoe_probit_batch_64uneven_f32_plus_16chains_N1e6_p1000_bf16"
+    return {
+        "workload": workload,
         "value": round(batched, 1),
         "unit": "chain-sweeps/s",
-        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "chains": nchains, "datasets": len(ds) + 1,
         "ms_per_step": round(1e3 * elapsed / a.steps, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
-        "data": "synthetic",
-        "config": {"workload": "horseshoe_probit_batch_64uneven_f32_plus_16chains_N1e6_p1000_bf16",
-                   "chains": nchains, "datasets": len(ds) + 1},
+        "batched_sweep_ms_events": round(ms_ev, 4),
         "plain_chain_sweeps_per_s": round(plain, 1),
         "batched_over_plain": round(batched / plain, 3),
+        "algorithmic_bytes_per_step": nbytes,
+        "roofline": roofline(nbytes, ms_ev, stored_traffic(traffic_path, workload)),
     }
-    b.close()
-    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -161,14 +344,9 @@ def main():
         print("bench.py runs on one GPU only: the library has no multi-GPU path (several GPUs "
               "would each sweep a row shard of X and sum X^T z across them).", file=sys.stderr)
         sys.exit(2)
-    if a.batch:
-        run_batch(a)
-        return
-    import numpy as np
     import torch
 
     import synth
-    from paper_1608_04329_amd import hsp
 
     torch.cuda.set_device(0)
     if a.copy_calibration:
@@ -181,77 +359,55 @@ def main():
         print(f"[bench] copy calibration: 2 copies of {a.copy_calibration} MiB", file=sys.stderr,
               flush=True)
         del src, dst
+
+    common = {"metric": METRIC, "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic"}
+    if a.only == "batch":
+        r = run_batch(a, a.traffic_json)
+        out = dict(common, value=r["value"], unit=r["unit"], ms_per_step=r["ms_per_step"], dtype="f32+bf16",
+                   config={"workload": r["workload"], "chains": r["chains"], "datasets": r["datasets"]},
+                   roofline=r["roofline"], batch=r)
+        print(json.dumps(out), flush=True)
+        return
+
+    if a.only == "rare":
+        r = run_rare(a)
+        out = dict(common, value=r["value"], unit=r["unit"], ms_per_step=round(1e3 / r["value"], 5),
+                   dtype="f32", config={"workload": r["workload"]}, roofline=r["roofline"], rare_event=r)
+        out["steps"], out["warmup"] = r["sweeps"], 0
+        print(json.dumps(out), flush=True)
+        return
+
     t0 = time.perf_counter()
-    beta_true, idx = synth.sparse_beta(a.p, min(10, a.p - 1), 13)
+    beta_true, _ = synth.sparse_beta(a.p, min(10, a.p - 1), 13)
     d = synth.probit_design(a.N, a.p, beta_true, 13, True, f"n{a.N}_p{a.p}")
     print(f"[bench] data N={a.N} p={a.p} generated in {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
 
-    t0 = time.perf_counter()
-    s = hsp.Sampler(d.X, d.y, seed=1, x_type=a.x_type, max_draws=max(64, a.steps + a.warmup))
-    print(f"[bench] sampler created (X copied, Gram formed) in {time.perf_counter() - t0:.1f}s",
-          file=sys.stderr, flush=True)
+    if a.only == "bf16":
+        r = run_single(a, d, "bf16", a.traffic_json)
+        out = dict(common, value=r["value"], unit=r["unit"], ms_per_step=r["ms_per_step"], dtype="bf16",
+                   config={"workload": r["workload"], "N": a.N, "p": a.p, "x_storage": "bf16"},
+                   roofline=r["roofline"], bf16=r)
+        print(json.dumps(out), flush=True)
+        return
 
-    s.sweep(a.warmup)
-    s.sync()
-    s.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.sweep(a.steps)
-    s.sync()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    zpass_ms, sweep_ms, n_timed = s.timing()
-    clamps, maxatt = s.counters()
-    s.set_timing(False)
-    ceil_ms, ceil_bytes = hsp.hsp_read_ceiling(s.h, 10)
-    print(f"[bench] {a.steps} sweeps in {elapsed:.3f}s; sweep kernel {zpass_ms:.4f} ms per launch, "
-          f"{sweep_ms:.4f} ms per sweep (events)", file=sys.stderr, flush=True)
-
-    esz = 4 if a.x_type == "f32" else 2
-    zbytes = a.N * a.p * esz + a.N  # X once, y once
-    value = a.steps / elapsed
-    achieved = zbytes / (zpass_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(a.traffic_json):
-        try:
-            t = json.load(open(a.traffic_json))
-            if (t.get("workload") == d.name and t.get("x_type") == a.x_type
-                    and t.get("kernel_fingerprint") == kernel_fingerprint()):
-                traffic = t.get("bytes_per_launch")
-        except (OSError, ValueError):
-            traffic = None
-    out = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "sweeps/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": round(1e3 * elapsed / a.steps, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if a.x_type == "f32" else "bf16",
-        "data": "synthetic",
-        "config": {"workload": f"horseshoe_probit_gibbs_N{a.N}_p{a.p}_x{a.x_type}",
-                   "N": a.N, "p": a.p, "x_storage": a.x_type, "n_side_arith": "f32",
-                   "p_side_arith": "f64", "chains": 1},
-        "hbm_gbps": round(zbytes / (elapsed / a.steps) / 1e9, 1),
-        "kernel_ms": round(zpass_ms, 5),
-        "sweep_ms_events": round(sweep_ms, 5),
-        "kernel_fingerprint": kernel_fingerprint(),
-        "read_ceiling": {"gbps": round(ceil_bytes / (ceil_ms * 1e-3) / 1e9, 1),
-                         "ms_per_pass": round(ceil_ms, 5),
-                         "kernel": "plain 16-byte non-temporal streaming read of the same X"},
-        "max_tn_proposals": int(maxatt),
-        "lambda_clamps": int(clamps),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic},
-    }
-    s.close()
-    if not a.no_cpu_baseline:
+    f32 = run_single(a, d, "f32", a.traffic_json)
+    out = dict(common, value=f32["value"], unit="sweeps/s", ms_per_step=f32["ms_per_step"], dtype="f32",
+               config={"workload": f32["workload"], "N": a.N, "p": a.p, "x_storage": "f32",
+                       "n_side_arith": "f32", "p_side_arith": "f64", "chains": 1},
+               hbm_gbps=f32["hbm_gbps"], kernel_ms=f32["kernel_ms"], sweep_ms_events=f32["sweep_ms_events"],
+               kernel_fingerprint=kernel_fingerprint(), read_ceiling=f32["read_ceiling"],
+               max_tn_proposals=f32["max_tn_proposals"], lambda_clamps=f32["lambda_clamps"],
+               roofline=f32["roofline"])
+    if a.only != "f32":
+        out["bf16"] = run_single(a, d, "bf16", a.traffic_json)
+        if a.N == 1_000_000 and a.p == 1000:
+            data = batch_data(d)
+            out["batch"] = run_batch(a, a.traffic_json, data)
+            del data
+            out["rare_event"] = run_rare(a)
+    if not a.no_cpu_baseline and a.only is None:
         print("[bench] timing the float64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(d, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -85,6 +85,10 @@ typedef struct {
                                last z step for hsp_get_debug (costs N*8 bytes
                                of writes per sweep) */
     int32_t use_graph;      /* 1 (default): replay sweeps from a captured HIP graph */
+    int32_t multi_chain_z;  /* batches: 1 (default) = chains sharing a bfloat16 design
+                               with rows of at most 1024 elements run one z pass for
+                               up to 16 of them (X beta and X^T z as matrix-core
+                               products); 0 = every chain its own z pass */
 } hsp_options;
 
 void hsp_default_options(hsp_options* opt);
@@ -137,6 +141,10 @@ hsp_status hsp_sweep(hsp_state* s, int64_t n_iter);
 hsp_status hsp_sync(hsp_state* s);
 
 /*
+ * The Monte-Carlo output (Section 5: the draws of each iteration are
+ * written out while the next iterations run, so the GPU never waits on the
+ * host).  Here the kept draws stay in a device-resident ring (288 GB of HBM
+ * hold long chains) and are copied out on request.
  * Copy kept draws [first, first + count) (0-based, in recording order since
  * creation or the last hsp_set_state) into host buffers: beta (count x p),
  * tau_m2 (count), lam_m2 (count x p, only if record_lambda, else may be
@@ -156,13 +164,21 @@ hsp_status hsp_destroy(hsp_state* s);
 const char* hsp_last_error(const hsp_state* s);
 
 /* ---- Batches: many independent chains, one graph launch per sweep ----------
+ * (A batch is its own handle, hsp_batch, created by hsp_batch_create; its
+ * chains are reached as ordinary hsp_state handles through hsp_batch_chain,
+ * so every state entry point applies to them.)
  * A batch runs chains of the same sweep on several designs at once (the
  * chains of one design share its library copy of X, y and G = X^T X).  One
  * hsp_batch_sweep advances every chain by the same number of sweeps; each
  * batched sweep is a single replay of a captured HIP graph holding every
  * chain's sweep kernel, one after another on the batch's stream.  Chain i
  * (dataset-major order) uses Philox counter word 3 = opt->chain_id + i, so it
- * draws exactly what a lone sampler created with that chain id draws. */
+ * draws exactly what a lone sampler created with that chain id draws --
+ * except chains that share a bfloat16 design under multi_chain_z: their
+ * X beta and X^T z run as bfloat16 matrix-core products with beta and z
+ * split into two bfloat16 parts each (error <= 2^-18 relative per term, then
+ * float32 accumulation).  They follow the same conditionals and counters, are
+ * bit-reproducible run to run, but round differently from a lone chain. */
 typedef struct hsp_batch hsp_batch; /* opaque, owned by the library */
 
 typedef struct {
@@ -203,7 +219,8 @@ hsp_status hsp_batch_destroy(hsp_batch* b);
 
 /* ---- Markov state: checkpoint / resume and test hooks --------------------- */
 /* Copy the Markov state to host buffers (beta, lam_m2, nu_m1: p doubles;
- * any pointer may be NULL).  Synchronises. */
+ * any pointer may be NULL).  Synchronises; a device failure found while
+ * synchronising poisons the state, hence the non-const handle. */
 hsp_status hsp_get_state(hsp_state* s, double* beta, double* lam_m2, double* nu_m1,
                          double* tau_m2, double* xi_m1, uint64_t* sweep);
 /* Overwrite the Markov state from host buffers; sweep is the number of
@@ -227,8 +244,9 @@ enum {
 hsp_status hsp_step(hsp_state* s, uint32_t which);
 
 /* Debug outputs of the last z step (needs debug_store_z): z (N floats),
- * attempt (N int32: 0-based index of the accepted proposal, bit 30 set for
- * the Gaussian branch), b = X^T z (p doubles).  NULL skips an output. */
+ * attempt (N int32: 0-based index of the accepted proposal, up to 4095, with
+ * bit 30 set when the row took the Gaussian branch; 32 bits hold both), b =
+ * X^T z (p doubles).  NULL skips an output. */
 hsp_status hsp_get_debug(hsp_state* s, float* z, int32_t* attempt, double* b);
 
 /* G = X^T X (p x p doubles, host). */
@@ -247,54 +265,6 @@ hsp_status hsp_get_counters(hsp_state* s, uint64_t* lambda_clamps, uint32_t* max
  * their durations to a running sum. */
 hsp_status hsp_set_timing(hsp_state* s, int32_t enable);
 hsp_status hsp_get_timing(hsp_state* s, double* zpass_ms, double* sweep_ms, int64_t* n_sweeps);
-
-/* Diagnostics: when enabled, every launch of the sweep kernel stores, per
- * block of its p-side group, a timestamp at the start (slot 0); then, in
- * order from slot 1 up to slot 447, one value per event: a timestamp for each
- * group barrier passed, and for each factorisation task (p > 16) its index + 1
- * in the task lists of hsp_tile_schedule plus one, then timestamps of when its
- * inputs were ready, its input tiles were loaded and it was done; from slot
- * 448, five records of 12 slots for the diagonal tiles the block factored
- * (loaded, after each of the four panels and their updates, stored); and in
- * the last slot the moment the z pass was seen complete.
- * hsp_get_phase_trace copies group_blocks x slots uint64 values of the last
- * launch; ticks_per_us converts the timestamps.  Enabling drops the captured
- * graph. */
-hsp_status hsp_set_phase_trace(hsp_state* s, int32_t enable);
-hsp_status hsp_get_phase_trace(hsp_state* s, uint64_t* out, int64_t* group_blocks, int64_t* slots,
-                               double* ticks_per_us);
-
-/* The factorisation schedule for p > 16 (host only, no device work): the
- * Cholesky factorisation of Q by 64 x 64 tiles (Section 5, beta step iii),
- * with the same row operations applied to an identity block, is split into
- * tile tasks that the p-side blocks of the sweep kernel run.  nt =
- * ceil(p / 64) tiles per side, gp blocks.
- * Task code: type (bits 0-1: 0 factor a diagonal tile, 1 triangular solve of
- * a tile of the block row, 2 tile update, 3 the next diagonal tile's solve,
- * update and factorisation in one block) | part (bit 2: 0 U, 1 L^-1) | step
- * k (bits 3-9) | tile row i (bits 10-16) | tile column j (bits 17-23).
- * With gp = 1, off[0..1] delimits block 0's list; with gp > 1, off[0..1]
- * delimits block 0's list (the critical chain) and off[1..2] the shared
- * queue that the other blocks claim tasks from, in order.  tasks (capacity
- * cap) receives the lists, off (3 entries) their bounds, *n_tasks the total
- * count (also when cap is too small, then HSP_ERANGE).  Errors: HSP_EINVAL
- * if nt < 1, nt > 64 or gp < 1.  Test hook for the schedule's coverage and
- * deadlock freedom. */
-hsp_status hsp_tile_schedule(int64_t nt, int64_t gp, uint32_t* tasks, int64_t cap, uint32_t* off,
-                             int64_t* n_tasks);
-
-/* Read ceiling of this GPU for the state's design: the mean milliseconds of
- * one pass of a plain streaming read (16-byte non-temporal loads, nothing
- * else) over the library's copy of X (N x ld elements), over `iters` passes
- * after two untimed ones, timed with HIP events on the state's stream.  The
- * z pass reads the same bytes; this bounds what it can reach.  Synchronises.
- * Errors: HSP_EINVAL if iters < 1; HSP_EPOISONED; HSP_EHIP. */
-hsp_status hsp_read_ceiling(hsp_state* s, int32_t iters, double* ms_per_pass, double* bytes_per_pass);
-
-/* Philox4x32-10 on the device: out[4i..4i+3] = Philox(ctr[4i..4i+3], key =
- * seed).  ctr and out are host arrays of 4n words.  Test hook for the
- * generator's bit-exactness. */
-hsp_status hsp_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,69 @@
+/*
+ * hsp_diag.h -- diagnostic and test hooks of the Horseshoe Probit sampler
+ * (include/hsp.h).  None of these is needed to run a chain: they expose the
+ * device Philox generator (for bit-exactness tests), the factorisation's
+ * task schedule (for its coverage and deadlock-freedom tests), a per-block
+ * phase trace of the sweep kernel, and a read-ceiling probe of the GPU.
+ * Same conventions as hsp.h.
+ */
+#ifndef HSP_DIAG_H
+#define HSP_DIAG_H
+
+#include "hsp.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Diagnostics: when enabled, every launch of the sweep kernel stores, per
+ * block of its p-side group, a timestamp at the start (slot 0); then, in
+ * order from slot 1 up to slot 447, one value per event: a timestamp for each
+ * group barrier passed, and for each factorisation task (p > 16) its index
+ * in the task lists of hsp_tile_schedule plus one, then timestamps of when its
+ * inputs were ready, its input tiles were loaded and it was done; from slot
+ * 448, five records of 12 slots for the diagonal tiles the block factored
+ * (loaded, after each of the four panels and their updates, stored); and in
+ * the last slot the moment the z pass was seen complete.
+ * hsp_get_phase_trace copies group_blocks x slots uint64 values of the last
+ * launch; ticks_per_us converts the timestamps.  Enabling drops the captured
+ * graph. */
+hsp_status hsp_set_phase_trace(hsp_state* s, int32_t enable);
+hsp_status hsp_get_phase_trace(hsp_state* s, uint64_t* out, int64_t* group_blocks, int64_t* slots,
+                               double* ticks_per_us);
+
+/* The factorisation schedule for p > 16 (host only, no device work): the
+ * Cholesky factorisation of Q by 64 x 64 tiles (Section 5, beta step iii),
+ * with the same row operations applied to an identity block, is split into
+ * tile tasks that the p-side blocks of the sweep kernel run.  nt =
+ * ceil(p / 64) tiles per side, gp blocks.
+ * Task code: type (bits 0-1: 0 factor a diagonal tile, 1 triangular solve of
+ * a tile of the block row, 2 tile update, 3 the next diagonal tile's solve,
+ * update and factorisation in one block) | part (bit 2: 0 U, 1 L^-1) | step
+ * k (bits 3-9) | tile row i (bits 10-16) | tile column j (bits 17-23).
+ * With gp = 1, off[0..1] delimits block 0's list; with gp > 1, off[0..1]
+ * delimits block 0's list (the critical chain) and off[1..2] the shared
+ * queue that the other blocks claim tasks from, in order.  tasks (capacity
+ * cap) receives the lists, off (3 entries) their bounds, *n_tasks the total
+ * count (also when cap is too small, then HSP_ERANGE).  Errors: HSP_EINVAL
+ * if nt < 1, nt > 64 or gp < 1.  Test hook for the schedule's coverage and
+ * deadlock freedom. */
+hsp_status hsp_tile_schedule(int64_t nt, int64_t gp, uint32_t* tasks, int64_t cap, uint32_t* off,
+                             int64_t* n_tasks);
+
+/* Read ceiling of this GPU for the state's design: the mean milliseconds of
+ * one pass of a plain streaming read (16-byte non-temporal loads, nothing
+ * else) over the library's copy of X (N x ld elements), over `iters` passes
+ * after two untimed ones, timed with HIP events on the state's stream.  The
+ * z pass reads the same bytes; this bounds what it can reach.  Synchronises.
+ * Errors: HSP_EINVAL if iters < 1; HSP_EPOISONED; HSP_EHIP. */
+hsp_status hsp_read_ceiling(hsp_state* s, int32_t iters, double* ms_per_pass, double* bytes_per_pass);
+
+/* Philox4x32-10 on the device: out[4i..4i+3] = Philox(ctr[4i..4i+3], key =
+ * seed).  ctr and out are host arrays of 4n words.  Test hook for the
+ * generator's bit-exactness. */
+hsp_status hsp_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -33,6 +33,30 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads for the N-sized loops (the z step, X^T z, the Gram).  Each loop is
+ * split so that every sum keeps its sequential order, so the results are the
+ * same bits for any number of threads. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
@@ -192,6 +216,7 @@ void orc_z_step(const void* X, int xtype, const uint8_t* y, int64_t N, int64_t p
                 const double* beta, uint64_t seed, uint32_t sweep, uint32_t chain,
                 double* z, int32_t* attempt, int32_t* branch)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         double eta = orc_row_dot(X, xtype, p, i, beta);
         int32_t a = 0, br = 0;
@@ -201,21 +226,31 @@ void orc_z_step(const void* X, int xtype, const uint8_t* y, int64_t N, int64_t p
     }
 }
 
+/* b_j = sum_i x_ij z_i, summed over i in order.  Threads own blocks of 64
+ * columns (each still summed row by row, in order). */
 void orc_xtz(const void* X, int xtype, int64_t N, int64_t p, const double* z, double* b)
 {
-    for (int64_t j = 0; j < p; ++j) b[j] = 0.0;
-    for (int64_t i = 0; i < N; ++i)
-        for (int64_t j = 0; j < p; ++j) b[j] += xval(X, xtype, i * p + j) * z[i];
+    const int64_t nblk = (p + 63) / 64;
+#pragma omp parallel for schedule(static)
+    for (int64_t blk = 0; blk < nblk; ++blk) {
+        const int64_t j0 = 64 * blk, j1 = j0 + 64 < p ? j0 + 64 : p;
+        for (int64_t j = j0; j < j1; ++j) b[j] = 0.0;
+        for (int64_t i = 0; i < N; ++i)
+            for (int64_t j = j0; j < j1; ++j) b[j] += xval(X, xtype, i * p + j) * z[i];
+    }
 }
 
+/* G_jk = sum_i x_ij x_ik, summed over i in order; threads own rows j of G. */
 void orc_gram(const void* X, int xtype, int64_t N, int64_t p, double* G)
 {
-    for (int64_t j = 0; j < p * p; ++j) G[j] = 0.0;
-    for (int64_t i = 0; i < N; ++i)
-        for (int64_t j = 0; j < p; ++j) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < p; ++j) {
+        for (int64_t k = 0; k < p; ++k) G[j * p + k] = 0.0;
+        for (int64_t i = 0; i < N; ++i) {
             double xj = xval(X, xtype, i * p + j);
             for (int64_t k = 0; k < p; ++k) G[j * p + k] += xj * xval(X, xtype, i * p + k);
         }
+    }
 }
 
 double orc_gram_entry(const void* X, int xtype, int64_t N, int64_t p, int64_t j, int64_t k)

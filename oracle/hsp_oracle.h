@@ -44,6 +44,10 @@ enum { ORC_X_F32 = 0, ORC_X_BF16 = 1 };
 /* Branch codes reported by orc_tn_draw. */
 enum { ORC_BRANCH_ROBERT = 0, ORC_BRANCH_GAUSS = 1 };
 
+/* Threads of the N-sized loops (OpenMP; results do not depend on it). */
+void orc_set_threads(int n);
+int  orc_max_threads(void);
+
 /* ---- random numbers (Section 5, RNG discussion) ------------------------ */
 void   orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double orc_uniform(uint32_t w);

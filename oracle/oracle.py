@@ -38,6 +38,8 @@ def lib():
         L = C.CDLL(path)
         i64, u64, u32, i32, d = C.c_int64, C.c_uint64, C.c_uint32, C.c_int32, C.c_double
         vp = C.c_void_p
+        L.orc_set_threads.argtypes = [C.c_int]; L.orc_set_threads.restype = None
+        L.orc_max_threads.argtypes = []; L.orc_max_threads.restype = C.c_int
         L.orc_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
         L.orc_uniform.argtypes = [u32]; L.orc_uniform.restype = d
         L.orc_words.argtypes = [u64, u32, u32, u32, u32, u32, _u32p]
@@ -93,6 +95,15 @@ def _f64(a):
 
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def set_threads(n):
+    """Threads of the oracle's N-sized loops (results are identical for any n)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads():
+    return lib().orc_max_threads()
 
 
 # ---- random numbers --------------------------------------------------------

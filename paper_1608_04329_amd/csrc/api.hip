@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/hsp.h"
+#include "../../include/hsp_diag.h"
 #include "hsp_internal.hpp"
 
 using namespace hsp;
@@ -275,7 +276,7 @@ hsp_status upload_state(hsp_state* s, const double* beta, const double* lam, con
                         double tau, double xi) {
     const uint32_t p = s->x.p;
     std::vector<float> b32(s->x.ld, 0.0f);
-    for (uint32_t j = 0; j < p; ++j) b32[j] = (float)(beta[j] / s->xscale_h[j]);
+    for (uint32_t j = 0; j < p; ++j) b32[j] = (float)(beta[j] * s->xscale_h[j]);
     HIP_TRY(hipMemcpy(s->beta, beta, p * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->beta32, b32.data(), s->x.ld * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(s->lam, lam, p * sizeof(double), hipMemcpyHostToDevice));
@@ -528,6 +529,7 @@ void hsp_default_options(hsp_options* o) {
     o->hip_stream = nullptr;
     o->debug_store_z = 0;
     o->use_graph = 1;
+    o->multi_chain_z = 1;
 }
 
 int64_t hsp_max_p(void) { return kMaxP; }
@@ -572,6 +574,13 @@ struct Pack {
     int xtype = 0;
     int chunks = 1;  // 16-byte vectors per lane per row: the largest of the pack's chains
     uint32_t blocks = 0;
+    // chains sharing one bfloat16 design: a multi-chain z pass (its own
+    // launch, mc_gz blocks) precedes the launch of their p-side groups
+    bool mc = false;
+    McArgs* dmc = nullptr;          // device copy of the pass's description
+    double* mc_partial = nullptr;   // mc_gz x kMcChains x ld
+    uint32_t* mc_count = nullptr;   // group and unit counters
+    uint32_t mc_gz = 0, mc_ld = 0;
     std::vector<size_t> chains;             // indices into hsp_batch::chains
     std::vector<uint32_t> gp, gz;           // the pack's blocks per chain
     SweepArgs* dargs = nullptr;             // one launch description per chain (device)
@@ -598,6 +607,9 @@ void free_batch(hsp_batch* b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
     for (Pack& pk : b->packs) {
+        if (pk.dmc) (void)hipFree(pk.dmc);
+        if (pk.mc_partial) (void)hipFree(pk.mc_partial);
+        if (pk.mc_count) (void)hipFree(pk.mc_count);
         if (pk.dargs) (void)hipFree(pk.dargs);
         if (pk.dtab) (void)hipFree(pk.dtab);
         if (pk.dmap) (void)hipFree(pk.dmap);
@@ -655,12 +667,49 @@ uint32_t count_tasks(uint32_t nt) {
 // columns are zeros), so a chain draws in a pack what it draws alone.
 hsp_status plan_packs(hsp_batch* b) {
     const int num_cus = b->chains[0]->num_cus;
+    std::vector<bool> taken(b->chains.size(), false);
+    // Chains that share a bfloat16 design (at least two, rows of at most
+    // kMcMaxLd elements) run the multi-chain z pass, up to kMcChains at a time.
+    if (b->chains[0]->opt.multi_chain_z) {
+        for (size_t i = 0; i < b->chains.size(); ++i) {
+            const hsp_state* own = b->chains[i];
+            if (own->owner || own->x.xtype != HSP_X_BF16 || own->x.ld > kMcMaxLd) continue;
+            std::vector<size_t> same;
+            for (size_t j = 0; j < b->chains.size(); ++j)
+                if (j == i || b->chains[j]->owner == own) same.push_back(j);
+            if (same.size() < 2) continue;
+            for (size_t g0 = 0; g0 < same.size(); g0 += kMcChains) {
+                Pack pk;
+                pk.xtype = HSP_X_BF16;
+                pk.chunks = own->plan.chunks;
+                pk.mc = true;
+                pk.mc_ld = own->x.ld;
+                // one block per claimed unit at most, two per compute unit
+                const uint32_t units = ((own->x.N + kMcRows - 1) / kMcRows + kMcUnit - 1) / kMcUnit;
+                pk.mc_gz = std::max<uint32_t>(1, std::min<uint32_t>(2u * (uint32_t)num_cus, units));
+                for (size_t j = g0; j < std::min(same.size(), g0 + kMcChains); ++j) {
+                    pk.chains.push_back(same[j]);
+                    taken[same[j]] = true;
+                }
+                // the p-side groups share the launch that follows the pass
+                const int cap = pack_capacity(HSP_X_BF16, pk.chunks, num_cus);
+                if (cap < (int)pk.chains.size()) return batch_fail(b, HSP_EHIP, "no resident capacity for a pack");
+                const uint32_t nt = own->x.p > (uint32_t)kSmallP ? (own->x.p + kTile - 1) / kTile : 0;
+                const uint32_t gmax = nt ? std::min<uint32_t>(kMaxGroup, nt * (nt + 1) / 2) : 1;
+                const uint32_t each = std::max<uint32_t>(1, std::min<uint32_t>(gmax, cap / pk.chains.size()));
+                pk.gp.assign(pk.chains.size(), each);
+                pk.gz.assign(pk.chains.size(), 0);
+                pk.blocks = each * (uint32_t)pk.chains.size();
+                b->packs.push_back(std::move(pk));
+            }
+        }
+    }
     for (int xt = 0; xt < 2; ++xt)
     for (int R : {8, 4, 2}) {
         std::vector<size_t> ids;
         int chunks = 1;
         for (size_t i = 0; i < b->chains.size(); ++i)
-            if (b->chains[i]->x.xtype == xt && rows_for_chunks(b->chains[i]->plan.chunks) == R) {
+            if (!taken[i] && b->chains[i]->x.xtype == xt && rows_for_chunks(b->chains[i]->plan.chunks) == R) {
                 ids.push_back(i);
                 chunks = std::max(chunks, b->chains[i]->plan.chunks);
             }
@@ -733,7 +782,8 @@ hsp_status plan_packs(hsp_batch* b) {
         uint32_t blk = 0;
         for (size_t j = 0; j < nc; ++j) {
             hsp_state* s = b->chains[pk.chains[j]];
-            SweepArgs h = sweep_args(s, kModeSweep);
+            // a chain of a multi-chain pack takes b from the pass before
+            SweepArgs h = sweep_args(s, pk.mc ? (kModeSweep & ~kModeZ) | kModeBsum : kModeSweep);
             h.gp = pk.gp[j];
             h.gz = pk.gz[j];
             h.zgroups = (h.gz + kZGroup - 1) / kZGroup;
@@ -762,6 +812,24 @@ hsp_status plan_packs(hsp_batch* b) {
             hipMemcpy(pk.dtab, tab.data(), nc * sizeof(const SweepArgs*), hipMemcpyHostToDevice) ||
             hipMemcpy(pk.dmap, map.data(), map.size() * 2, hipMemcpyHostToDevice))
             return batch_fail(b, HSP_EHIP, "pack upload");
+        if (pk.mc) {
+            const hsp_state* own = b->chains[pk.chains[0]];
+            McArgs m{};
+            m.x = own->x;
+            m.y = dev_ptr(static_cast<const uint8_t*>(own->y));
+            m.nchains = (uint32_t)nc;
+            m.gz = pk.mc_gz;
+            m.zgroups = (m.gz + kZGroup - 1) / kZGroup;
+            const size_t ncount = (size_t)m.zgroups + 64;
+            if (dalloc(&pk.dmc, 1) || dalloc(&pk.mc_partial, (size_t)m.gz * kMcChains * pk.mc_ld) ||
+                dalloc(&pk.mc_count, ncount))
+                return batch_fail(b, HSP_ENOMEM, "pack allocation failed");
+            m.partial = dev_ptr(pk.mc_partial);
+            m.count = dev_ptr(pk.mc_count);
+            for (size_t j = 0; j < nc; ++j) m.chain[j] = dev_ptr(static_cast<const SweepArgs*>(pk.dargs + j));
+            if (hipMemset(pk.mc_count, 0, ncount * 4) || hipMemcpy(pk.dmc, &m, sizeof m, hipMemcpyHostToDevice))
+                return batch_fail(b, HSP_EHIP, "pack upload");
+        }
     }
     return HSP_OK;
 }
@@ -861,7 +929,8 @@ hsp_status hsp_batch_sweep(hsp_batch* b, int64_t n) {
         hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
         for (size_t i = 0; !e && i < b->packs.size(); ++i) {
             const Pack& pk = b->packs[i];
-            e = pack_launch(pk.xtype, pk.chunks, pk.dtab, pk.dmap, pk.blocks, b->stream);
+            if (pk.mc) e = mc_launch(pk.dmc, pk.mc_ld, pk.mc_gz, b->stream);
+            if (!e) e = pack_launch(pk.xtype, pk.chunks, pk.dtab, pk.dmap, pk.blocks, b->stream);
         }
         hipError_t e2 = hipStreamEndCapture(b->stream, &g);
         if (!e) e = e2;

@@ -96,6 +96,7 @@ enum : uint32_t {
     kModeNuXi = 16u,
     kModeRecord = 32u,   // write the draw of this sweep into the ring
     kModeAdvance = 64u,  // count the sweep as completed
+    kModeBsum = 128u,    // b = X^T z from bsum, accumulated by an earlier launch (no z pass here)
 };
 
 // Layout of X in device memory: row-major, leading dimension ld elements,
@@ -117,7 +118,7 @@ struct XLayout {
 struct SweepArgs {
     XLayout x;
     HSP_GLOBAL const uint8_t* y;
-    HSP_GLOBAL float* beta32;      // ld floats (padding zero): beta_j 2^-e_j for the z pass
+    HSP_GLOBAL float* beta32;      // ld floats (padding zero): beta_j 2^e_j for the z pass
     HSP_GLOBAL const double* xscale;  // p: 2^e_j, the scale of column j of the stored X
     HSP_GLOBAL double* partial;    // gz x ld: per-block float64 partials of X^T z
     HSP_GLOBAL double* bsum;       // ld: X^T z accumulated by the z groups (zero between launches)
@@ -157,6 +158,30 @@ struct SweepArgs {
 
 // Device view of a launch description.
 using Args = const HSP_CONST SweepArgs;
+
+// ---- the multi-chain z pass (several chains sharing one bfloat16 design) ----------
+// One pass over X serves up to kMcChains chains: X beta and X^T z for all of
+// them are bfloat16 matrix-core products (beta and z split into a high and a
+// low bfloat16 part each, float32 accumulation).  The four waves of a block
+// split the columns of a tile of kMcRows rows; each wave holds up to kMcKs
+// 32-column steps, so ld <= 4 * 32 * kMcKs.
+constexpr int kMcChains = 16;
+constexpr int kMcKs = 8;
+constexpr int kMcRows = 16;
+constexpr int kMcUnit = 64;  // tiles per claimed unit; each unit's X^T z is rounded to the grid
+constexpr uint32_t kMcMaxLd = 4u * 32u * kMcKs;
+
+struct McArgs {
+    XLayout x;                          // the shared design (bfloat16)
+    HSP_GLOBAL const uint8_t* y;
+    uint32_t nchains;                   // chains served (<= kMcChains)
+    uint32_t gz;                        // blocks of the launch
+    uint32_t zgroups;                   // ceil(gz / kZGroup)
+    HSP_GLOBAL double* partial;         // gz x kMcChains x ld float64 block partials of X^T z
+    HSP_GLOBAL uint32_t* count;         // [0, zgroups): group arrivals; [zgroups]: groups done;
+                                        // [zgroups + 32]: next unit (zero between launches)
+    HSP_GLOBAL const SweepArgs* chain[kMcChains];  // the chains' launch descriptions
+};
 
 // Diagnostic trace per group block: slot 0 = start, slots 1.. one value per
 // event in order (group barriers: a timestamp; per factorisation task: its
@@ -205,6 +230,10 @@ hipError_t sweep_launch(const SweepArgs& host, const SweepArgs* const* table, co
 int pack_capacity(int xtype, int chunks, int num_cus);
 hipError_t pack_launch(int xtype, int chunks, const SweepArgs* const* table, const uint16_t* chain_of_block,
                        uint32_t blocks, hipStream_t st);
+// The multi-chain z pass over a shared bfloat16 design (mc: device copy of
+// its description, gz blocks): every chain's X^T z is added into its bsum.
+// The chains' p-side groups follow in a launch of their own with kModeBsum.
+hipError_t mc_launch(const McArgs* mc, uint32_t ld, uint32_t gz, hipStream_t st);
 
 // G = X^T X (p x p float64, leading dimension p) of the stored X, unscaled
 // with the column exponents e (null: none).  The rows are cut into nsplit

@@ -356,13 +356,14 @@ __device__ void small_path(Args& a, Group& g, uint32_t k, double* lds) {
                 }
         }
     }
-    if (a.mode & kModeZ) {
-        if (threadIdx.x == 0) {
+    if (a.mode & (kModeZ | kModeBsum)) {
+        if ((a.mode & kModeZ) && threadIdx.x == 0) {
             wait_count(&a.ctrl->z_count, g.zbase + a.zgroups, a.ctrl, a.timeout_ticks, 64);
         }
         __syncthreads();
-        // b as the z groups accumulated it (in the units of the stored X,
-        // unscaled exactly); wave 0 takes it from LDS below
+        // b as the z groups (of this launch, or of an earlier multi-chain
+        // pass) accumulated it, in the units of the stored X, unscaled
+        // exactly; wave 0 takes it from LDS below
         for (uint32_t j = threadIdx.x; j < p; j += kThreads) {
             const double s = ldc(&a.bsum[j]) * a.xscale[j];
             a.b[j] = s;
@@ -384,7 +385,7 @@ __device__ void small_path(Args& a, Group& g, uint32_t k, double* lds) {
             if (j < p) {
                 const Words4 wd = draw_words(a.seed, j, k, kTagBetaS, 0, a.chain);
                 v[q] = box_muller_d(u01d(wd.w0), u01d(wd.w1));
-                w[q] = (a.mode & kModeZ) ? lds[kSmallBOff + j] : a.b[j];
+                w[q] = (a.mode & (kModeZ | kModeBsum)) ? lds[kSmallBOff + j] : a.b[j];
             }
         }
         wave_solve(U, p, v, false);  // U v = s
@@ -397,7 +398,7 @@ __device__ void small_path(Args& a, Group& g, uint32_t k, double* lds) {
             if (j < p) {
                 const double bj = w[q] + v[q];
                 a.beta[j] = bj;
-                a.beta32[j] = (float)(bj / a.xscale[j]);
+                a.beta32[j] = (float)(bj * a.xscale[j]);
                 if (!isfinite(bj)) nonfinite = true;
                 if (keep) a.ring_beta[(size_t)slot * p + j] = bj;
             }
@@ -902,7 +903,7 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
     for (uint32_t j = threadIdx.x; j < P; j += kThreads) {
         double s = 0.0;
         if (j < p) {
-            if (a.mode & kModeZ) {
+            if (a.mode & (kModeZ | kModeBsum)) {
                 s = ldc(&a.bsum[j]) * a.xscale[j];  // unscaled exactly
                 if (rank == 0) a.b[j] = s;
             } else {
@@ -996,7 +997,7 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
                     double bi = 0.0;
                     for (int q = 0; q < 16; ++q) bi += red[q * 17 + tc];
                     a.beta[col] = bi;
-                    a.beta32[col] = (float)(bi / a.xscale[col]);
+                    a.beta32[col] = (float)(bi * a.xscale[col]);
                     if (!isfinite(bi)) nonfinite = true;
                     if (keep) {
                         a.ring_beta[(size_t)slot * p + col] = bi;
@@ -1041,7 +1042,7 @@ __device__ __forceinline__ void pside_role(Args& a, uint32_t rank, uint32_t k, d
             for (uint32_t e = threadIdx.x; e < 2 * nt * nt; e += kThreads) a.ver[e] = 0u;
             if (threadIdx.x == 0) a.ctrl->task_next = 0u;
         }
-        if (a.mode & kModeZ) {
+        if (a.mode & (kModeZ | kModeBsum)) {
             // every block of the group has read b's accumulator (before the
             // barrier that follows y): clear it for the next launch
             if (threadIdx.x == 0) a.ctrl->z_next = 0u;

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <utility>
 
+#include "mc_dev.hpp"
 #include "pside_dev.hpp"
 #include "zpass_dev.hpp"
 
@@ -44,6 +45,15 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(const SweepArgs* con
 }
 
 
+
+// The multi-chain z pass for chains sharing one bfloat16 design (KS
+// 32-column steps per wave); no block waits for another.
+template <int KS>
+__global__ __launch_bounds__(kThreads, 2) void mc_zpass_kernel(const McArgs* __restrict__ mc) {
+    __shared__ double lds[kMcLdsDoubles];
+    McView& m = *(McView*)mc;
+    mc_role<KS>(m, blockIdx.x, lds);
+}
 
 using KernelFn = void (*)(const SweepArgs* const*, const uint16_t*);
 
@@ -110,6 +120,14 @@ int pack_capacity(int xtype, int chunks, int num_cus) {
                                                            kThreads, 0) != hipSuccess)
         return 0;
     return per_cu * num_cus;
+}
+
+hipError_t mc_launch(const McArgs* mc, uint32_t ld, uint32_t gz, hipStream_t st) {
+    if (ld > kMcMaxLd) return hipErrorInvalidValue;
+    void* args[] = {&mc};
+    const void* f = ld <= 4u * 32u * 4u ? reinterpret_cast<const void*>(&mc_zpass_kernel<4>)
+                                        : reinterpret_cast<const void*>(&mc_zpass_kernel<kMcKs>);
+    return hipLaunchKernel(f, dim3(gz), dim3(kThreads), args, 0, st);
 }
 
 hipError_t pack_launch(int xtype, int chunks, const SweepArgs* const* table, const uint16_t* chain_of_block,

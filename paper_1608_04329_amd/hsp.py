@@ -36,7 +36,7 @@ class hsp_options(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("chain_id", C.c_uint32), ("x_type", C.c_int32),
                 ("x_on_host", C.c_int32), ("record_lambda", C.c_int32), ("thin", C.c_int64),
                 ("max_draws", C.c_int64), ("hip_stream", C.c_void_p), ("debug_store_z", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("multi_chain_z", C.c_int32)]
 
 
 class hsp_dataset(C.Structure):
@@ -412,9 +412,10 @@ class Batch:
     """
 
     def __init__(self, datasets, chains=1, seed=1, chain_id=0, record_lambda=False, thin=1,
-                 max_draws=1024, debug_store_z=False, stream=None):
+                 max_draws=1024, debug_store_z=False, stream=None, multi_chain_z=True):
         load()
         opt = hsp_default_options()
+        opt.multi_chain_z = int(multi_chain_z)
         opt.seed = seed
         opt.chain_id = chain_id
         opt.debug_store_z = int(debug_store_z)

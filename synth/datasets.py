@@ -130,6 +130,31 @@ def eq13(N: int, p: int, seed: int) -> Dataset:
     return probit_design(N, p, leading_beta(p, EQ13_LEAD), seed, False, f"eq13_n{N}_p{p}")
 
 
+RARE_N, RARE_P, RARE_YBAR = 1_295_848, 141, 0.0048
+
+
+def rare_event(seed: int = 14, N: int = RARE_N, p: int = RARE_P, ybar: float = RARE_YBAR,
+               k_nonzero: int = 8) -> Dataset:
+    """Shape-matched stand-in for the paper's clinical data set (Section 6.2:
+    N = 1,295,848 rows, p = 141 predictors, mean(y) = 0.0048), which is not
+    available: an intercept column plus p - 1 iid N(0, 1) covariates,
+    k_nonzero covariate effects ~ U(-0.5, 0.5) at random indices, and the
+    intercept b0 set so that E[y] = ybar.  With x beta ~ N(0, s^2) over the
+    covariates, P(y = 1) = Phi(b0 / sqrt(1 + s^2)), so b0 = Phi^-1(ybar)
+    sqrt(1 + s^2), s^2 = sum of the squared effects."""
+    from statistics import NormalDist
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 11])))
+    beta = np.zeros(p)
+    idx = np.sort(rng.choice(np.arange(1, p), size=k_nonzero, replace=False))
+    beta[idx] = rng.uniform(-0.5, 0.5, size=k_nonzero)
+    s2 = float(np.sum(beta[1:] ** 2))
+    beta[0] = NormalDist().inv_cdf(ybar) * math.sqrt(1.0 + s2)
+    d = probit_design(N, p, beta, seed, True, f"rare_n{N}_p{p}")
+    d.info["nonzero_idx"] = idx.tolist()
+    d.info["target_ybar"] = ybar
+    return d
+
+
 def batch_shapes(n_datasets: int = 64, seed: int = 1000):
     """Uneven dataset shapes: N log-uniform in [1e4, 2e5], p uniform in {50..500}."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -7,13 +7,17 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "hsp.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(hsp_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(hsp_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -36,7 +40,8 @@ def test_host_only_entry_points():
     assert o.seed == 1 and o.thin == 1 and o.max_draws == 1024 and o.use_graph == 1
     assert hsp.hsp_max_p() >= 1000
     # the options struct has the C layout
-    assert ctypes.sizeof(hsp.hsp_options) == 56
+    assert o.multi_chain_z == 1
+    assert ctypes.sizeof(hsp.hsp_options) == 64
 
 
 def test_create_rejects_bad_shapes_before_touching_a_device():

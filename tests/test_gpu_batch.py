@@ -167,3 +167,93 @@ def test_batch_uneven_datasets(env):
         # the recovered sign of the large leading coefficient (4.0)
         assert st["beta"][1] > 0
     b.close()
+
+
+# ---- the multi-chain z pass (chains sharing a bfloat16 design) ----------------------
+def _flip_aware(orc, Xo, Xf, y, z, att, b, zo, ao, bo_branch, beta_prev):
+    """z on rows without a flip, and X^T z with the flipped rows' share in the bar."""
+    flips = ((att & ~(1 << 30)) != ao) | (((att & (1 << 30)) != 0) != (bo_branch == 1))
+    assert flips.sum() <= max(1, int(1e-5 * y.size))
+    ok = ~flips
+    assert np.max(np.abs(z[ok] - zo[ok]) / z_scale(Xf[ok], beta_prev)) < 1e-5
+    dz = np.abs(z.astype(np.float64) - zo)
+    dz[ok] = 0.0
+    slack = np.abs(Xf[flips].astype(np.float64)).T @ dz[flips] if flips.any() else 0.0
+    assert np.all(np.abs(b - orc.xtz(Xo, zo)) <= 1e-5 * b_scale(Xf, zo) + slack)
+
+
+@pytest.mark.parametrize("sets", [
+    [((3001, 1000, 71), "bf16", 16)],
+    [((5003, 200, 72), "bf16", 3), ((2500, 12, 73), "bf16", 2), ((1777, 1024, 74), "bf16", 2),
+     ((3001, 40, 75), "f32", 2)],
+])
+def test_multi_chain_pass_follows_the_oracle(env, orc, sets):
+    """Every chain of a multi-chain pass, sweep by sweep, against the oracle
+    on the bfloat16-rounded design: z and X^T z to the 1e-5 bars, beta to the
+    propagated bar, the hyperparameters to 1e-4."""
+    ds, b = make_batch(env, sets, seed=12, chain_id=7, debug_store_z=True)
+    ors = []
+    cid = 7
+    for d, xt, c in ds:
+        if xt == "bf16":
+            Xo = synth.bf16_bits(d.X).reshape(d.X.shape)
+            Xf = synth.bf16_to_f32(Xo).reshape(d.X.shape)
+        else:
+            Xo = Xf = d.X
+        G = orc.gram(Xo)
+        for _ in range(c):
+            ors.append((Xo, Xf, d.y, G, orc.Chain(d.p), cid))
+            cid += 1
+    for k in range(1, 3):
+        b.sweep(1)
+        b.sync()
+        for i, (Xo, Xf, y, G, ch, cid) in enumerate(ors):
+            beta_prev = ch.beta.copy()
+            zo, ao, bro = orc.z_step(Xo, y, beta_prev, 12, k, chain=cid)
+            zo2, bo, _ = ch.sweep_once(Xo, y, G, seed=12, chain=cid, want_z=True)
+            assert np.array_equal(zo, zo2)
+            z, att, bg = b.chain(i).debug()
+            assert np.all(z * (2.0 * y - 1.0) > 0), (k, i)
+            _flip_aware(orc, Xo, Xf, y, z, att, bg, zo, ao, bro, beta_prev)
+            g = b.chain(i).state()
+            assert g["sweep"] == ch.sweep == k
+            tol = beta_tol(G, ch.lam_m2, ch.tau_m2, Xf, zo, ch.beta) * 10
+            assert np.all(np.abs(g["beta"] - ch.beta) <= tol), (k, i)
+            for key, ref in [("lam_m2", ch.lam_m2), ("nu_m1", ch.nu_m1)]:
+                np.testing.assert_allclose(g[key], ref, rtol=1e-4)
+            assert g["tau_m2"] == pytest.approx(ch.tau_m2, rel=1e-4)
+    b.close()
+
+
+def test_multi_chain_pass_is_reproducible(env):
+    sets = [((4099, 300, 76), "bf16", 5), ((2051, 16, 77), "bf16", 3)]
+    outs = []
+    for _ in range(2):
+        _, b = make_batch(env, sets, seed=13, record_lambda=True)
+        b.sweep(5)
+        b.sync()
+        outs.append([b.chain(i).draws() for i in range(len(b))])
+        b.close()
+    for (b1, t1, l1, n1), (b2, t2, l2, n2) in zip(*outs):
+        assert n1 == n2 == 5
+        assert np.array_equal(b1, b2) and np.array_equal(t1, t2) and np.array_equal(l1, l2)
+
+
+def test_multi_chain_off_equals_lone_chains(env):
+    """With the multi-chain pass switched off, chains on a shared bfloat16
+    design draw bitwise what lone samplers draw."""
+    torch, hsp = env
+    sets = [((3001, 150, 78), "bf16", 3)]
+    ds, b = make_batch(env, sets, seed=14, chain_id=4, multi_chain_z=False)
+    b.sweep(3)
+    b.sync()
+    batch = [b.chain(i).draws() for i in range(len(b))]
+    b.close()
+    d, xt, _ = ds[0]
+    for i in range(3):
+        s = hsp.Sampler(torch.from_numpy(d.X).cuda(), torch.from_numpy(d.y).cuda(), seed=14,
+                        chain_id=4 + i, x_type=xt)
+        s.sweep(3)
+        bl, tl, _ = s.draws()
+        s.close()
+        assert np.array_equal(batch[i][0], bl) and np.array_equal(batch[i][1], tl)

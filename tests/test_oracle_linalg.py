@@ -124,3 +124,19 @@ def test_gram_fast_is_the_same_sum(orc):
         G, Gf = orc.gram(Xa), orc.gram_fast(Xa)
         scale = np.sqrt(np.outer(np.diag(G), np.diag(G)))
         assert np.max(np.abs(G - Gf) / scale) < 1e-13
+
+
+def test_threads_do_not_change_results(orc):
+    """The OpenMP loops keep every sum's order: one thread and many give the
+    same bits for the z step, X^T z and the Gram."""
+    import synth as _s
+    d = _s.probit_design(3000, 70, np.r_[1.0, np.zeros(69)], 5, True)
+    beta = np.random.default_rng(1).normal(0, 0.2, 70)
+    out = []
+    for t in (1, 4):
+        orc.set_threads(t)
+        z, a, br = orc.z_step(d.X, d.y, beta, 3, 2)
+        out.append((z, a, br, orc.xtz(d.X, z), orc.gram(d.X)))
+    orc.set_threads(orc.max_threads())
+    for u, v in zip(*out):
+        assert np.array_equal(u, v)

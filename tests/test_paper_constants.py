@@ -47,3 +47,13 @@ def test_memory_of_the_design_the_paper_could_not_run():
     g = GOLD["x_bytes_1e6_by_1e4"]
     N, p = g["N"], g["p"]
     assert N * p * 4 + N >= g["value_gb_lower_bound"] * 1e9
+
+
+def test_rare_event_stand_in_has_the_papers_shape():
+    """The synthetic stand-in for the Section 6.2 data has its shape and its
+    outcome rate (the data themselves are not available)."""
+    g = GOLD["real_data_shape"]
+    assert (synth.RARE_N, synth.RARE_P, synth.RARE_YBAR) == (g["N"], g["p"], g["ybar"])
+    d = synth.rare_event(N=200_000)
+    assert d.p == g["p"] and np.all(d.X[:, 0] == 1.0)
+    assert abs(d.y.mean() / g["ybar"] - 1.0) < 0.1
