@@ -310,22 +310,40 @@ double orc_xi_step(double tau_m2, uint64_t seed, uint32_t sweep, uint32_t chain)
 /* ------------------------------------------------------------------------ */
 /* Dense linear algebra, textbook forms.                                    */
 /* ------------------------------------------------------------------------ */
+/* Q = U^T U, U upper, row by row:
+ *   U_jj = sqrt(Q_jj - sum_{k<j} U_kj^2),
+ *   U_ji = (Q_ji - sum_{k<j} U_kj U_ki) / U_jj   (i > j),
+ * each sum taken in the order k = 0, 1, ..., j-1.  The entries of one row j
+ * depend only on rows above it, so they are computed on OpenMP threads; the
+ * factor is built in a work array holding U^T row-major (column j of U is a
+ * contiguous row there), which changes where the values sit, not what is
+ * summed or in which order. */
 int orc_cholesky_upper(int64_t p, const double* Q, double* U)
 {
-    for (int64_t k = 0; k < p * p; ++k) U[k] = 0.0;
-    for (int64_t j = 0; j < p; ++j) {
+    double* Lt = (double*)calloc((size_t)(p * p), sizeof(double)); /* Lt[i p + k] = U_ki */
+    int rc = 0;
+    for (int64_t j = 0; j < p && rc == 0; ++j) {
+        const double* uj = Lt + j * p;
         double d = Q[j * p + j];
-        for (int64_t k = 0; k < j; ++k) d -= U[k * p + j] * U[k * p + j];
-        if (!(d > 0.0)) return (int)(j + 1);
-        double ujj = sqrt(d);
-        U[j * p + j] = ujj;
+        for (int64_t k = 0; k < j; ++k) d -= uj[k] * uj[k];
+        if (!(d > 0.0)) {
+            rc = (int)(j + 1);
+            break;
+        }
+        const double ujj = sqrt(d);
+        Lt[j * p + j] = ujj;
+#pragma omp parallel for schedule(static) if (p - j > 256)
         for (int64_t i = j + 1; i < p; ++i) {
+            const double* ui = Lt + i * p;
             double s = Q[j * p + i];
-            for (int64_t k = 0; k < j; ++k) s -= U[k * p + j] * U[k * p + i];
-            U[j * p + i] = s / ujj;
+            for (int64_t k = 0; k < j; ++k) s -= uj[k] * ui[k];
+            Lt[i * p + j] = s / ujj;
         }
     }
-    return 0;
+    for (int64_t r = 0; r < p; ++r)
+        for (int64_t c = 0; c < p; ++c) U[r * p + c] = c >= r ? Lt[c * p + r] : 0.0;
+    free(Lt);
+    return rc;
 }
 
 void orc_solve_upper(int64_t p, const double* U, const double* r, double* x)
