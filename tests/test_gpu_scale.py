@@ -79,27 +79,40 @@ def test_scaled_columns_z_b_beta(env, orc, xt, N, p):
 
 @pytest.mark.parametrize("xt", ["f32", "bf16"])
 def test_scaled_columns_reproducible_and_whole_sweeps(env, orc, xt):
-    """Three whole sweeps follow the oracle; two runs agree bit for bit."""
+    """Three whole sweeps; two runs agree bit for bit, and every sweep matches
+    one oracle sweep from the GPU's own state before it (the single-sweep
+    bars).  Coefficients of the 2^-30 columns are set by the prior, so tau^-2
+    carries the other coefficients' X^T z rounding into them from one sweep to
+    the next (Eq. 12): a trajectory is compared sweep by sweep, not end to end."""
     torch, hsp = env
     X, y, scale = scaled_design(6007, 24, 520)
     Xo, Xf = matched(X, xt)
     runs = []
     for _ in range(2):
         s = hsp.Sampler(torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(), seed=3, x_type=xt,
-                        debug_store_z=True)
+                        debug_store_z=True, record_lambda=True)
         s.sweep(3)
         runs.append((s.draws(), s.debug()[2]))
         s.close()
-    (b1, t1, _), bb1 = runs[0]
-    (b2, t2, _), bb2 = runs[1]
-    assert np.array_equal(b1, b2) and np.array_equal(t1, t2) and np.array_equal(bb1, bb2)
+    (b1, t1, l1, _), bb1 = runs[0]
+    (b2, t2, l2, _), bb2 = runs[1]
+    assert np.array_equal(b1, b2) and np.array_equal(t1, t2) and np.array_equal(l1, l2)
+    assert np.array_equal(bb1, bb2)
     G = orc.gram(Xo)
-    ch = orc.Chain(24)
-    for k in range(3):
+    for k in range(1, 4):
+        if k == 1:
+            ch = orc.Chain(24)  # the cold start
+        else:
+            # the state after sweep k - 1: nu and xi are that sweep's draws from its
+            # lambda and tau (the same counters on both sides)
+            lam, tau = l1[k - 2], t1[k - 2]
+            ch = orc.Chain(24, beta=b1[k - 2], lam_m2=lam, nu_m1=orc.nu_step(lam, 3, k - 1),
+                           tau_m2=tau, xi_m1=orc.xi_step(tau, 3, k - 1), sweep=k - 1)
         zo, bo, _ = ch.sweep_once(Xo, y, G, seed=3, want_z=True)
-        tol = beta_tol(G, ch.lam_m2, ch.tau_m2, Xf, zo, ch.beta) * 10
-        assert np.all(np.abs(b1[k] - ch.beta) <= tol), k
-        assert t1[k] == pytest.approx(ch.tau_m2, rel=1e-4)
+        tol = beta_tol(G, ch.lam_m2, ch.tau_m2, Xf, zo, ch.beta)
+        assert np.all(np.abs(b1[k - 1] - ch.beta) <= tol), k
+        np.testing.assert_allclose(l1[k - 1], ch.lam_m2, rtol=1e-12)
+        assert t1[k - 1] == pytest.approx(ch.tau_m2, rel=1e-12)
     assert np.max(np.abs(bb1 - bo) / b_scale(Xf, zo)) < 1e-5
 
 
