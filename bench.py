@@ -26,6 +26,9 @@ line also carries
                 the paper ran, with the lag-1 autocorrelation and effective
                 sample size of the coefficients and the truncated-normal
                 branch mix
+  streamed      the same float32 workload with X in pinned host memory,
+                streamed through the GPU every sweep: its rate against the
+                measured host-to-device link
   read_ceiling  a plain streaming read of the same X (16-byte non-temporal
                 loads, nothing else) on this GPU: what the z pass could reach
   cpu_baseline  the float64 oracle timed on this host on a bounded sample of
@@ -53,9 +56,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--N", type=int, default=1_000_000)
     ap.add_argument("--p", type=int, default=1000)
-    ap.add_argument("--only", choices=["f32", "bf16", "batch", "rare"], default=None,
+    ap.add_argument("--only", choices=["f32", "bf16", "batch", "rare", "streamed"], default=None,
                     help="run one form only and print its own line (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="built-in launch shapes (no autotuner)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--traffic-json", default=TRAFFIC_JSON)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -167,9 +171,11 @@ def run_single(a, d, x_type, traffic_path):
 
     from paper_1608_04329_amd import hsp
     t0 = time.perf_counter()
-    s = hsp.Sampler(d.X, d.y, seed=1, x_type=x_type, max_draws=max(64, a.steps + a.warmup))
-    print(f"[bench] {x_type}: sampler created (X copied, Gram formed) in {time.perf_counter() - t0:.1f}s",
-          file=sys.stderr, flush=True)
+    s = hsp.Sampler(d.X, d.y, seed=1, x_type=x_type, max_draws=max(64, a.steps + a.warmup),
+                    autotune=not a.no_tune)
+    plan = s.plan()
+    print(f"[bench] {x_type}: sampler created (X copied, Gram formed, launch plan {plan[4]}) in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     s.sweep(a.warmup)
     s.sync()
     s.set_timing(True)
@@ -203,7 +209,47 @@ def run_single(a, d, x_type, traffic_path):
                          "kernel": "plain 16-byte non-temporal streaming read of the same X"},
         "max_tn_proposals": int(maxatt),
         "lambda_clamps": int(clamps),
+        "launch_plan": {"group_blocks": plan[0], "z_blocks": plan[1], "z_static_pct": plan[2],
+                        "z_unit": plan[3], "chosen": plan[4]},
         "roofline": roofline(nbytes, kernel_ms, stored_traffic(traffic_path, workload)),
+    }
+
+
+def run_streamed(a, d, sweeps=20):
+    """The same workload with X kept in pinned host memory and streamed through
+    the GPU in row chunks every sweep (the form for designs beyond device
+    memory): bound by the host-to-device link, reported against the link's
+    own measured rate."""
+    import torch
+
+    from paper_1608_04329_amd import hsp
+    t0 = time.perf_counter()
+    s = hsp.Sampler(d.X, d.y, seed=1, max_draws=64, x_stream=True)
+    print(f"[bench] streamed: sampler created (pinned copy, Gram) in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    s.sweep(2)
+    s.sync()
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.sweep(sweeps)
+    s.sync()
+    elapsed = time.perf_counter() - t0
+    _, sweep_ms, _ = s.timing()
+    s.set_timing(False)
+    link_ms, link_bytes = hsp.hsp_read_ceiling(s.h, 3)
+    s.close()
+    nbytes = d.N * d.p * 4 + d.N
+    link_gbps = link_bytes / (link_ms * 1e-3) / 1e9
+    achieved = nbytes / (sweep_ms * 1e-3) / 1e9
+    return {
+        "workload": f"horseshoe_probit_gibbs_N{d.N}_p{d.p}_xf32_streamed_from_host",
+        "value": round(sweeps / elapsed, 3), "unit": "sweeps/s", "sweeps": sweeps,
+        "ms_per_step": round(1e3 * elapsed / sweeps, 4),
+        "link_gbps_measured": round(link_gbps, 1),
+        "roofline": {"bound": "host-to-device link", "achieved": round(achieved, 1), "peak": round(link_gbps, 1),
+                     "unit": "GB/s", "frac": round(achieved / link_gbps, 4), "traffic": None,
+                     "peak_source": "plain host-to-device copies of the same pinned X, measured in this run"},
     }
 
 
@@ -295,7 +341,7 @@ def run_batch(a, traffic_path, data=None):
     datasets = [(torch.from_numpy(d.X).cuda(), torch.from_numpy(d.y).cuda(), "f32") for d in ds]
     datasets.append((torch.from_numpy(big.X).cuda(), torch.from_numpy(big.y).cuda(), "bf16"))
     counts = [1] * len(ds) + [16]
-    b = hsp.Batch(datasets, counts, seed=1, max_draws=64)
+    b = hsp.Batch(datasets, counts, seed=1, max_draws=64, autotune=not a.no_tune)
     del datasets
     torch.cuda.empty_cache()
     nchains = len(b)
@@ -309,6 +355,7 @@ def run_batch(a, traffic_path, data=None):
     elapsed = time.perf_counter() - t0
     ms_ev, _ = b.timing()
     b.set_timing(False)
+    bplan = b.plan()
     batched = nchains * a.steps / elapsed
     print(f"[bench] batch: {a.steps} sweeps of {nchains} chains in {elapsed:.3f}s "
           f"({ms_ev:.3f} ms per batched sweep by events)", file=sys.stderr, flush=True)
@@ -333,6 +380,8 @@ def run_batch(a, traffic_path, data=None):
         "batched_sweep_ms_events": round(ms_ev, 4),
         "plain_chain_sweeps_per_s": round(plain, 1),
         "batched_over_plain": round(batched / plain, 3),
+        "launch_plan": {"mc_blocks": bplan[0], "z_bandwidth_pct": bplan[1], "packs": bplan[2],
+                        "chosen": bplan[3]},
         "algorithmic_bytes_per_step": nbytes,
         "roofline": roofline(nbytes, ms_ev, stored_traffic(traffic_path, workload)),
     }
@@ -384,6 +433,14 @@ def main():
     print(f"[bench] data N={a.N} p={a.p} generated in {time.perf_counter() - t0:.1f}s",
           file=sys.stderr, flush=True)
 
+    if a.only == "streamed":
+        r = run_streamed(a, d)
+        out = dict(common, value=r["value"], unit=r["unit"], ms_per_step=r["ms_per_step"], dtype="f32",
+                   config={"workload": r["workload"], "N": a.N, "p": a.p}, roofline=r["roofline"], streamed=r)
+        out["steps"], out["warmup"] = r["sweeps"], 2
+        print(json.dumps(out), flush=True)
+        return
+
     if a.only == "bf16":
         r = run_single(a, d, "bf16", a.traffic_json)
         out = dict(common, value=r["value"], unit=r["unit"], ms_per_step=r["ms_per_step"], dtype="bf16",
@@ -407,6 +464,7 @@ def main():
             out["batch"] = run_batch(a, a.traffic_json, data)
             del data
             out["rare_event"] = run_rare(a)
+            out["streamed"] = run_streamed(a, d)
     if not a.no_cpu_baseline and a.only is None:
         print("[bench] timing the float64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(d, a.cpu_seconds)

@@ -89,9 +89,32 @@ typedef struct {
                                with rows of at most 1024 elements run one z pass for
                                up to 16 of them (X beta and X^T z as matrix-core
                                products); 0 = every chain its own z pass */
+    int32_t autotune;       /* 1: pick the launch shapes by measurement (see below);
+                               0 (default): the built-in shapes */
+    int32_t x_stream;       /* 1: keep the library's copy of X in pinned host memory
+                               and stream it through the GPU in row chunks every
+                               sweep (designs larger than device memory); 0 (default):
+                               X resident in device memory */
+    int64_t stream_rows;    /* with x_stream: rows per chunk (rounded to the row
+                               splits of the one-time X^T X); 0 (default): about
+                               256 MB of X per chunk */
 } hsp_options;
 
 void hsp_default_options(hsp_options* opt);
+
+/*
+ * Autotuning.  With autotune = 1, hsp_create (and hsp_batch_create's first
+ * hsp_batch_sweep) picks how the sweep kernel splits its work -- the blocks
+ * of the p-side group, and how the z pass deals out its row tiles (a share
+ * statically, the rest in claimed units); for a batch, the blocks of each
+ * multi-chain z pass and the balance of z-pass and p-side blocks in its
+ * packs -- by timing a few sweeps of each candidate on the device.  The
+ * chain's state is restored afterwards, and no choice changes any draw:
+ * a tuned chain draws bit for bit what an untuned one draws.  If the
+ * environment variable HSP_TUNE_CACHE names a file, a choice found there for
+ * the same device, shape and library is used without measuring, and new
+ * choices are added to it (a text file of "key<TAB>value" lines).
+ */
 
 /*
  * Create a sampler state from the design X (N x p float32, row-major,
@@ -100,6 +123,12 @@ void hsp_default_options(hsp_options* opt);
  * (rows padded to 16 bytes, converted to bfloat16 if requested).  Computes
  * G = X^T X once in float64 (Section 5, beta step i) and sets the cold start
  * of Section 6.1 (beta = 0; lambda = nu = tau = xi = 1).
+ * With x_stream, the library's copy of X lives in pinned host memory and
+ * every sweep streams it through two device chunk buffers (copies on a
+ * stream of their own, overlapped with the z pass of the previous chunk);
+ * the chain draws bit for bit what a resident chain draws whenever the row
+ * splits of X^T X are the same (always when about 256 MB of X holds one
+ * split).  Throughput is then bound by the host-to-device link.
  * Errors: HSP_EINVAL if N < 2, p < 2, N >= 2^32, p > hsp_max_p(), a y_i is
  * not 0/1 or an X entry is not finite; HSP_ENOMEM; HSP_EHIP.
  */
@@ -171,7 +200,8 @@ const char* hsp_last_error(const hsp_state* s);
  * chains of one design share its library copy of X, y and G = X^T X).  One
  * hsp_batch_sweep advances every chain by the same number of sweeps; each
  * batched sweep is a single replay of a captured HIP graph holding every
- * chain's sweep kernel, one after another on the batch's stream.  Chain i
+ * chain's sweep kernel, one after another on the batch's stream (every
+ * dataset of a batch is resident: x_stream is ignored).  Chain i
  * (dataset-major order) uses Philox counter word 3 = opt->chain_id + i, so it
  * draws exactly what a lone sampler created with that chain id draws --
  * except chains that share a bfloat16 design under multi_chain_z: their

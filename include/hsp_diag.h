@@ -3,7 +3,8 @@
  * (include/hsp.h).  None of these is needed to run a chain: they expose the
  * device Philox generator (for bit-exactness tests), the factorisation's
  * task schedule (for its coverage and deadlock-freedom tests), a per-block
- * phase trace of the sweep kernel, and a read-ceiling probe of the GPU.
+ * phase trace of the sweep kernel, a read-ceiling probe of the GPU, and the
+ * autotuner's plan and cache.
  * Same conventions as hsp.h.
  */
 #ifndef HSP_DIAG_H
@@ -62,6 +63,30 @@ hsp_status hsp_read_ceiling(hsp_state* s, int32_t iters, double* ms_per_pass, do
  * seed).  ctr and out are host arrays of 4n words.  Test hook for the
  * generator's bit-exactness. */
 hsp_status hsp_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out);
+
+/* The launch plan a state sweeps with: blocks of the p-side group and of the
+ * z pass, the share of z-pass row tiles dealt out statically (percent) and
+ * the tiles per claimed unit of the rest; note (capacity note_cap, may be
+ * NULL) receives how the plan was chosen ("built-in", or the autotuner's
+ * choice and whether it was measured or read from the cache). */
+hsp_status hsp_get_plan(hsp_state* s, int64_t* group_blocks, int64_t* z_blocks, int64_t* static_pct,
+                        int64_t* unit, char* note, int64_t note_cap);
+
+/* The launch shapes of a batch's packs: blocks of each multi-chain z pass
+ * (0: the built-in two per compute unit), the z-pass bandwidth per block that
+ * the pack split model assumes (percent of nominal), the number of packs
+ * (0 until the first hsp_batch_sweep), and how they were chosen. */
+hsp_status hsp_batch_get_plan(hsp_batch* b, int64_t* mc_blocks, int64_t* bw_pct, int64_t* packs, char* note,
+                              int64_t note_cap);
+
+/* The autotuner's cache key of a state (its device, shape and plan format). */
+hsp_status hsp_tune_key(hsp_state* s, char* key, int64_t cap);
+
+/* The autotuner's cache file (host only, no device work): store value under
+ * key (replacing an earlier entry of that key; keys hold no tab or newline,
+ * values no newline), and read it back (HSP_ERANGE if absent). */
+hsp_status hsp_tune_cache_put(const char* path, const char* key, const char* value);
+hsp_status hsp_tune_cache_get(const char* path, const char* key, char* value, int64_t cap);
 
 #ifdef __cplusplus
 }

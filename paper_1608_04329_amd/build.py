@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhsp.so")
-SOURCES = ["api.hip", "sweep.hip", "gram.hip", "schedule.cpp"]
+SOURCES = ["api.hip", "sweep.hip", "gram.hip", "schedule.cpp", "tune.cpp"]
 ARCH = os.environ.get("HSP_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <string>
@@ -12,6 +13,7 @@
 #include "../../include/hsp.h"
 #include "../../include/hsp_diag.h"
 #include "hsp_internal.hpp"
+#include "tune.hpp"
 
 using namespace hsp;
 
@@ -121,6 +123,19 @@ struct hsp_state {
     bool in_batch = false;             // owned by an hsp_batch (not destroyed alone)
     bool timing = false;
     EventTimer timer;  // timed sweeps
+    std::string plan_note;  // how the launch plan was chosen (autotuner)
+    // X streamed from pinned host memory in row chunks (x_stream)
+    bool streamed = false;
+    void* Xhost = nullptr;              // N x ld library layout, pinned
+    void* stage[2] = {nullptr, nullptr};  // device chunk buffers
+    uint32_t chunk_rows = 0, nchunks = 0;
+    hipStream_t copy_stream = nullptr;  // the chunks' host-to-device copies
+    hipEvent_t copied[2] = {nullptr, nullptr}, freed[2] = {nullptr, nullptr};
+    bool freed_used[2] = {false, false};
+    SweepArgs* sdargs = nullptr;        // nchunks z-pass launches + the p-side launch (device)
+    const SweepArgs** sdtab = nullptr;
+    std::vector<SweepArgs> sd_host;     // host copies of the same
+    uint32_t sd_mode = 0;               // the mode they were built for (0: none yet)
 };
 
 namespace {
@@ -268,6 +283,18 @@ void free_state(hsp_state* s) {
                     s->zgrp_count, s->dargs, s->dtab, s->tasks, s->task_off, s->ver};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
+    if (s->streamed) {
+        // s->Xbuf is null for a streamed state: X lives in Xhost and the stages
+        if (s->Xhost) (void)hipHostFree(s->Xhost);
+        for (int i = 0; i < 2; ++i) {
+            if (s->stage[i]) (void)hipFree(s->stage[i]);
+            if (s->copied[i]) (void)hipEventDestroy(s->copied[i]);
+            if (s->freed[i]) (void)hipEventDestroy(s->freed[i]);
+        }
+        if (s->sdargs) (void)hipFree(s->sdargs);
+        if (s->sdtab) (void)hipFree(s->sdtab);
+        if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+    }
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -300,6 +327,180 @@ hsp_status set_counters(hsp_state* s, uint64_t sweep) {
 }
 
 hsp_status chain_impl(hsp_state* s);
+
+// The factorisation's task lists for the plan's group size (tile path).
+hsp_status upload_schedule(hsp_state* s) {
+    const uint32_t nt = (s->x.p + kTile - 1) / kTile;
+    std::vector<uint32_t> tasks, off;
+    chol_schedule(nt, s->plan.gp, &tasks, &off);
+    if (s->tasks) (void)hipFree(s->tasks);
+    if (s->task_off) (void)hipFree(s->task_off);
+    s->tasks = s->task_off = nullptr;
+    HIP_TRY(dalloc(&s->tasks, tasks.size()));
+    HIP_TRY(dalloc(&s->task_off, off.size()));
+    HIP_TRY(hipMemcpy(s->tasks, tasks.data(), tasks.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(s->task_off, off.data(), off.size() * 4, hipMemcpyHostToDevice));
+    return HSP_OK;
+}
+
+// Switch the state to another launch plan (the next sweep uses it).
+hsp_status apply_plan(hsp_state* s, const SweepPlan& plan) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const bool regroup = plan.gp != s->plan.gp;
+    s->plan = plan;
+    if (regroup && s->x.p > (uint32_t)kSmallP) {
+        hsp_status st = upload_schedule(s);
+        if (st) return st;
+    }
+    SweepArgs h;
+    HIP_TRY(put_args(s, kModeSweep, 0, &h));
+    if (s->graph) {
+        (void)hipGraphExecDestroy(s->graph);
+        s->graph = nullptr;
+    }
+    return HSP_OK;
+}
+
+std::string device_tag(int device, int num_cus) {
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
+    for (char& c : arch)
+        if (c == '\t' || c == ' ' || c == '\n') c = '_';
+    return arch + " cus=" + std::to_string(num_cus);
+}
+
+// Cache key of a single chain's plan: the device, the shape and the plan format.
+std::string sweep_tune_key(const hsp_state* s) {
+    return "sweep-v1 " + device_tag(s->device, s->num_cus) + " xt=" + std::to_string(s->x.xtype) +
+           " N=" + std::to_string(s->x.N) + " p=" + std::to_string(s->x.p);
+}
+
+const char* tune_cache_path() {
+    const char* p = std::getenv("HSP_TUNE_CACHE");
+    return (p && *p) ? p : nullptr;
+}
+
+// Mean milliseconds of `timed` launches of the sweep kernel after `warm`
+// untimed ones, on the state's stream.
+hsp_status time_sweeps(hsp_state* s, int warm, int timed, double* ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    for (int i = 0; !e && i < warm; ++i) e = enqueue_sweep(s, s->stream);
+    if (!e) e = hipEventRecord(e0, s->stream);
+    for (int i = 0; !e && i < timed; ++i) e = enqueue_sweep(s, s->stream);
+    if (!e) e = hipEventRecord(e1, s->stream);
+    if (!e) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (!e) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    HIP_TRY(e);
+    *ms = (double)t / timed;
+    return check_device_flags(s);
+}
+
+// The Markov state and control block of a chain, kept on the host while the
+// autotuner runs sweeps, then put back.
+struct SavedChain {
+    std::vector<double> beta, lam, nu;
+    double tau = 0.0, xi = 0.0;
+    Ctrl ctrl{};
+};
+
+hsp_status save_chain(hsp_state* s, SavedChain* c) {
+    const size_t p = s->x.p;
+    c->beta.resize(p);
+    c->lam.resize(p);
+    c->nu.resize(p);
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipMemcpy(c->beta.data(), s->beta, p * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(c->lam.data(), s->lam, p * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(c->nu.data(), s->nu, p * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&c->tau, s->tau, 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&c->xi, s->xi, 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&c->ctrl, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    return HSP_OK;
+}
+
+hsp_status restore_chain(hsp_state* s, const SavedChain& c) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    hsp_status st = upload_state(s, c.beta.data(), c.lam.data(), c.nu.data(), c.tau, c.xi);
+    if (st) return st;
+    HIP_TRY(hipMemcpy(s->ctrl, &c.ctrl, sizeof(Ctrl), hipMemcpyHostToDevice));
+    return HSP_OK;
+}
+
+// A plan read back from the cache, if it is one this state can run.
+bool plan_from_text(hsp_state* s, const std::string& v, SweepPlan* out) {
+    long gp = 0, pct = 0, unit = 0;
+    if (!tune_parse(v, "gp", &gp) || !tune_parse(v, "pct", &pct) || !tune_parse(v, "unit", &unit)) return false;
+    if (gp < 1 || pct < 0 || pct > 100 || unit < 1 || unit > (long)kZUnitMax) return false;
+    SweepPlan pl;
+    if (sweep_plan(s->x, s->num_cus, &pl, (uint32_t)gp) != hipSuccess || pl.gp != (uint32_t)gp) return false;
+    pl.static_pct = (uint32_t)pct;
+    pl.unit = (uint32_t)unit;
+    *out = pl;
+    return true;
+}
+
+std::string plan_text(const SweepPlan& pl) {
+    return "gp=" + std::to_string(pl.gp) + " pct=" + std::to_string(pl.static_pct) + " unit=" +
+           std::to_string(pl.unit);
+}
+
+// The autotuner for one chain: the p-side group size and how the z pass deals
+// out its tiles, by timing a few sweeps of every candidate (or from the cache).
+hsp_status tune_impl(hsp_state* s) {
+    const std::string key = sweep_tune_key(s);
+    const char* path = tune_cache_path();
+    std::string cached;
+    SweepPlan pl;
+    if (path && tune_cache_get(path, key, &cached) && plan_from_text(s, cached, &pl)) {
+        s->plan_note = plan_text(pl) + " (cache)";
+        return apply_plan(s, pl);
+    }
+    SavedChain saved;
+    hsp_status st = save_chain(s, &saved);
+    if (st) return st;
+    const uint32_t gmax = max_group(s->x, s->plan.capacity);
+    std::vector<uint32_t> gps{gmax};
+    if (s->x.p > (uint32_t)kSmallP)
+        for (uint32_t pct : {75u, 50u, 33u}) {
+            const uint32_t g = std::max<uint32_t>(1, (gmax * pct + 50) / 100);
+            if (std::find(gps.begin(), gps.end(), g) == gps.end()) gps.push_back(g);
+        }
+    // shorter runs for big designs: every candidate sweeps all of X
+    const double bytes = (double)s->x.N * s->x.ld * (s->x.xtype == 0 ? 4 : 2);
+    const int timed = bytes > 1e9 ? 4 : 8;
+    SweepPlan best = s->plan;
+    double best_ms = 1e300;
+    for (uint32_t gp : gps)
+        for (uint32_t pct : {0u, 40u, 75u})
+            for (uint32_t unit : {4u, 8u, 16u}) {
+                SweepPlan c;
+                HIP_TRY(sweep_plan(s->x, s->num_cus, &c, gp));
+                c.static_pct = pct;
+                c.unit = unit;
+                st = apply_plan(s, c);
+                double ms = 0.0;
+                if (!st) st = time_sweeps(s, 2, timed, &ms);
+                if (st) return st;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+    st = apply_plan(s, best);
+    if (!st) st = restore_chain(s, saved);
+    if (st) return st;
+    char buf[64];
+    std::snprintf(buf, sizeof buf, " ms=%.4f", best_ms);
+    s->plan_note = plan_text(best) + buf + " (measured)";
+    if (path) (void)tune_cache_put(path, key, plan_text(best) + buf);
+    return HSP_OK;
+}
 
 // Device, stream and wait bound of a new state.
 hsp_status setup_impl(hsp_state* s) {
@@ -412,6 +613,184 @@ hsp_status create_impl(hsp_state* s, const float* X, const uint8_t* y, int64_t N
     return chain_impl(s);
 }
 
+// X kept in pinned host memory and streamed through the GPU (x_stream).
+// Creation makes two passes over X in chunks of whole Gram row splits, with
+// the same kernels as the resident path: the column maxima, then each chunk
+// scaled (and rounded to bfloat16) into the library layout, validated, its
+// Gram partial tiles formed, and copied out to the pinned buffer.  G is then
+// summed over the splits in order, as for a resident X.
+hsp_status create_stream_impl(hsp_state* s, const float* X, const uint8_t* y, int64_t N, int64_t p) {
+    hsp_status st0 = setup_impl(s);
+    if (st0) return st0;
+    s->streamed = true;
+    const int xt = s->opt.x_type;
+    const uint32_t align = xt == HSP_X_F32 ? 4 : 8;
+    const uint32_t ld = (uint32_t)((p + align - 1) / align * align);
+    const size_t esz = xt == HSP_X_F32 ? 4 : 2;
+    const size_t row_bytes = (size_t)ld * esz;
+    uint64_t budget = s->opt.stream_rows > 0 ? (uint64_t)s->opt.stream_rows
+                                             : std::max<uint64_t>(64, ((uint64_t)256 << 20) / row_bytes);
+    budget = std::max<uint64_t>(64, budget / 64 * 64);
+    XLayout full{};
+    full.xtype = xt;
+    full.N = (uint32_t)N;
+    full.p = (uint32_t)p;
+    full.ld = ld;
+    const GramGeometry gg = gram_geometry(full, s->num_cus, budget);
+    const uint64_t per = std::max<uint64_t>(1, budget / gg.rows_per_split);
+    s->chunk_rows = (uint32_t)std::min<uint64_t>((uint64_t)gg.rows_per_split * per,
+                                                 ((uint64_t)N + 63) / 64 * 64);
+    s->nchunks = (uint32_t)(((uint64_t)N + s->chunk_rows - 1) / s->chunk_rows);
+    HIP_TRY(hipHostMalloc(&s->Xhost, (size_t)N * row_bytes, hipHostMallocDefault));
+    for (int i = 0; i < 2; ++i) HIP_TRY(dalloc(reinterpret_cast<char**>(&s->stage[i]), (size_t)s->chunk_rows * row_bytes));
+    s->x = full;
+    s->x.X = dev_ptr(static_cast<const void*>(s->stage[0]));
+    HIP_TRY(dalloc(&s->y, (size_t)N));
+    HIP_TRY(dalloc(&s->ctrl, 1));
+    HIP_TRY(hipMemsetAsync(s->ctrl, 0, sizeof(Ctrl), s->stream));
+    const hipMemcpyKind kind = s->opt.x_on_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    HIP_TRY(hipMemcpyAsync(s->y, y, (size_t)N, kind, s->stream));
+    HIP_TRY(dalloc(&s->xexp, (size_t)p));
+    HIP_TRY(dalloc(&s->xscale, (size_t)p));
+    // float32 source of a chunk: the caller's device X in place, or a staged host chunk
+    float* raw = nullptr;
+    if (s->opt.x_on_host) HIP_TRY(dalloc(&raw, (size_t)s->chunk_rows * p));
+    uint32_t* cm = nullptr;
+    double* work = nullptr;
+    hipError_t e = dalloc(&cm, (size_t)p);
+    auto source = [&](uint32_t c, uint32_t* rows) -> const float* {
+        const size_t r0 = (size_t)c * s->chunk_rows;
+        *rows = (uint32_t)std::min<size_t>(s->chunk_rows, (size_t)N - r0);
+        if (!raw) return X + r0 * p;
+        if (!e) e = hipMemcpyAsync(raw, X + r0 * p, (size_t)*rows * p * 4, kind, s->stream);
+        return raw;
+    };
+    if (!e) e = hipMemsetAsync(cm, 0, (size_t)p * 4, s->stream);
+    for (uint32_t c = 0; !e && c < s->nchunks; ++c) {
+        uint32_t rows = 0;
+        const float* src = source(c, &rows);
+        if (!e) e = colmax_launch(src, rows, (uint32_t)p, cm, s->stream);
+    }
+    std::vector<uint32_t> bits(p);
+    if (!e) e = hipMemcpyAsync(bits.data(), cm, (size_t)p * 4, hipMemcpyDeviceToHost, s->stream);
+    if (!e) e = hipStreamSynchronize(s->stream);
+    std::vector<int32_t> ex(p, 0);
+    s->xscale_h.assign(p, 1.0);
+    for (int64_t j = 0; !e && j < p; ++j) {
+        if (bits[j] == 0 || bits[j] >= 0x7F800000u) continue;
+        float m;
+        std::memcpy(&m, &bits[j], 4);
+        int k = 0;
+        const float f = std::frexp(m, &k);
+        ex[j] = f == 0.5f ? k - 1 : k;
+        s->xscale_h[j] = std::ldexp(1.0, ex[j]);
+    }
+    if (!e) e = hipMemcpyAsync(s->xexp, ex.data(), (size_t)p * 4, hipMemcpyHostToDevice, s->stream);
+    if (!e) e = hipMemcpyAsync(s->xscale, s->xscale_h.data(), (size_t)p * 8, hipMemcpyHostToDevice, s->stream);
+    if (!e) e = dalloc(&work, (size_t)gg.nsplit * gg.npairs * kTile * kTile);
+    for (uint32_t c = 0; !e && c < s->nchunks; ++c) {
+        uint32_t rows = 0;
+        const float* src = source(c, &rows);
+        XLayout cl = full;
+        cl.X = dev_ptr(static_cast<const void*>(s->stage[0]));
+        cl.N = rows;
+        const size_t r0 = (size_t)c * s->chunk_rows;
+        if (!e) e = pack_x_launch(src, cl, s->xexp, s->stream);
+        if (!e) e = validate_launch(cl, s->y + r0, s->ctrl, s->stream);
+        if (!e) e = gram_chunk_launch(cl, gg, (uint32_t)(r0 / gg.rows_per_split), work, s->stream);
+        if (!e) e = hipMemcpyAsync(static_cast<char*>(s->Xhost) + r0 * row_bytes, s->stage[0], rows * row_bytes,
+                                   hipMemcpyDeviceToHost, s->stream);
+        if (!e) e = hipStreamSynchronize(s->stream);  // the stage and raw buffers are reused
+    }
+    if (!e) e = dalloc(&s->G, (size_t)p * p);
+    if (!e) e = gram_reduce_launch(work, gg, (uint32_t)p, s->xexp, s->G, s->stream);
+    const size_t P = ((size_t)p + kTile - 1) / kTile * kTile;
+    if (!e && p > kSmallP) e = dalloc(&s->Gp, P * P);
+    if (!e && s->Gp) e = pad_gram_launch(s->G, (uint32_t)p, (uint32_t)P, s->Gp, s->stream);
+    if (!e) e = hipStreamSynchronize(s->stream);
+    if (cm) (void)hipFree(cm);
+    if (work) (void)hipFree(work);
+    if (raw) (void)hipFree(raw);
+    HIP_TRY(e);
+    {
+        Ctrl c;
+        HIP_TRY(hipMemcpy(&c, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+        if (c.err & kErrInput)
+            return fail(nullptr, HSP_EINVAL,
+                        "y must hold only 0/1 and X must be finite (also after bfloat16 rounding)");
+    }
+    HIP_TRY(hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking));
+    for (int i = 0; i < 2; ++i) {
+        HIP_TRY(hipEventCreateWithFlags(&s->copied[i], hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&s->freed[i], hipEventDisableTiming));
+    }
+    return chain_impl(s);
+}
+
+// The launch descriptions of a streamed sweep in `mode`: one z-pass launch
+// per chunk (no p-side group; the chunk's rows, its first global row and its
+// device buffer), then the p-side launch, which takes X^T z from the
+// accumulator the chunks added into.
+hsp_status stream_args(hsp_state* s, uint32_t mode) {
+    if (s->sd_mode == mode && s->sdargs) return HSP_OK;
+    HIP_TRY(hipStreamSynchronize(s->stream));  // launches in flight read the old ones
+    const uint32_t nc = s->nchunks;
+    if (!s->sdargs) {
+        HIP_TRY(dalloc(&s->sdargs, (size_t)nc + 1));
+        HIP_TRY(dalloc(&s->sdtab, (size_t)nc + 1));
+        std::vector<const SweepArgs*> tab(nc + 1);
+        for (uint32_t i = 0; i <= nc; ++i) tab[i] = s->sdargs + i;
+        HIP_TRY(hipMemcpy(s->sdtab, tab.data(), tab.size() * sizeof(SweepArgs*), hipMemcpyHostToDevice));
+    }
+    s->sd_host.assign(nc + 1, SweepArgs{});
+    for (uint32_t c = 0; c < nc; ++c) {
+        SweepArgs h = sweep_args(s, kModeZ);
+        sweep_finish_args(&h, s->plan);
+        const uint32_t r0 = c * s->chunk_rows;
+        const uint32_t rows = std::min(s->chunk_rows, s->x.N - r0);
+        h.x.X = dev_ptr(static_cast<const void*>(s->stage[c & 1]));
+        h.x.N = rows;
+        h.first_row = r0;
+        h.gp = 0;
+        const uint32_t tiles = (rows + s->plan.rows - 1) / s->plan.rows;
+        h.gz = std::max<uint32_t>(1, std::min<uint32_t>(s->plan.gz, (tiles + 3) / 4));
+        h.zgroups = (h.gz + kZGroup - 1) / kZGroup;
+        s->sd_host[c] = h;
+    }
+    const uint32_t pmode = (mode & ~kModeZ) | ((mode & kModeZ) ? kModeBsum : 0u);
+    SweepArgs h = sweep_args(s, pmode);
+    sweep_finish_args(&h, s->plan);
+    s->sd_host[nc] = h;
+    HIP_TRY(hipMemcpy(s->sdargs, s->sd_host.data(), (nc + 1) * sizeof(SweepArgs), hipMemcpyHostToDevice));
+    s->sd_mode = mode;
+    return HSP_OK;
+}
+
+// One streamed sweep: chunk c is copied into buffer c % 2 on the copy stream
+// once the z pass of chunk c - 2 has released it, and its z pass waits for
+// the copy; then the p-side launch.
+hsp_status enqueue_stream(hsp_state* s, uint32_t mode) {
+    hsp_status st = stream_args(s, mode);
+    if (st) return st;
+    const size_t row_bytes = (size_t)s->x.ld * (s->x.xtype == 0 ? 4 : 2);
+    if (mode & kModeZ) {
+        for (uint32_t c = 0; c < s->nchunks; ++c) {
+            const int slot = c & 1;
+            const SweepArgs& h = s->sd_host[c];
+            if (s->freed_used[slot]) HIP_TRY(hipStreamWaitEvent(s->copy_stream, s->freed[slot], 0));
+            HIP_TRY(hipMemcpyAsync(s->stage[slot], static_cast<const char*>(s->Xhost) + (size_t)h.first_row * row_bytes,
+                                   (size_t)h.x.N * row_bytes, hipMemcpyHostToDevice, s->copy_stream));
+            HIP_TRY(hipEventRecord(s->copied[slot], s->copy_stream));
+            HIP_TRY(hipStreamWaitEvent(s->stream, s->copied[slot], 0));
+            HIP_TRY(sweep_launch(h, s->sdtab + c, s->plan, s->stream));
+            HIP_TRY(hipEventRecord(s->freed[slot], s->stream));
+            s->freed_used[slot] = true;
+        }
+    }
+    HIP_TRY(sweep_launch(s->sd_host[s->nchunks], s->sdtab + s->nchunks, s->plan, s->stream));
+    return HSP_OK;
+}
+
 // A further chain on the data of `owner` (same X, y, G; its own Markov state,
 // draw ring, factorisation buffers and control block).
 hsp_status clone_impl(hsp_state* s, const hsp_state* owner) {
@@ -453,21 +832,20 @@ hsp_status chain_impl(hsp_state* s) {
     HIP_TRY(dalloc(&s->vec, 2 * (size_t)p + 8));
 
     HIP_TRY(sweep_plan(s->x, s->num_cus, &s->plan));
+    s->plan_note = "built-in";
     if (p > kSmallP) {
         // the factorisation's task lists for the group, and its tile versions
         const uint32_t nt = (uint32_t)(P / kTile);
-        std::vector<uint32_t> tasks, off;
-        chol_schedule(nt, s->plan.gp, &tasks, &off);
-        HIP_TRY(dalloc(&s->tasks, tasks.size()));
-        HIP_TRY(dalloc(&s->task_off, off.size()));
         HIP_TRY(dalloc(&s->ver, 2 * (size_t)nt * nt));
-        HIP_TRY(hipMemcpy(s->tasks, tasks.data(), tasks.size() * 4, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(s->task_off, off.data(), off.size() * 4, hipMemcpyHostToDevice));
         HIP_TRY(hipMemsetAsync(s->ver, 0, 2 * (size_t)nt * nt * 4, s->stream));
+        hsp_status st = upload_schedule(s);
+        if (st) return st;
     }
-    HIP_TRY(dalloc(&s->partial, (size_t)s->plan.gz * ld));
+    // z-pass partials and group counters for the largest split any plan uses
+    const size_t gz_cap = (size_t)s->plan.capacity;
+    HIP_TRY(dalloc(&s->partial, gz_cap * ld));
     {
-        const size_t ng = (s->plan.gz + kZGroup - 1) / kZGroup;
+        const size_t ng = (gz_cap + kZGroup - 1) / kZGroup;
         HIP_TRY(dalloc(&s->bsum, ld));
         HIP_TRY(hipMemsetAsync(s->bsum, 0, ld * sizeof(double), s->stream));
         HIP_TRY(dalloc(&s->zgrp_count, ng));
@@ -503,6 +881,11 @@ hsp_status chain_impl(hsp_state* s) {
     st = set_counters(s, 0);
     if (st) return st;
     HIP_TRY(hipStreamSynchronize(s->stream));
+    if (s->streamed) {
+        s->plan_note = "streamed (built-in)";
+        return HSP_OK;
+    }
+    if (s->opt.autotune && !s->in_batch) return tune_impl(s);
     return HSP_OK;
 }
 
@@ -530,6 +913,7 @@ void hsp_default_options(hsp_options* o) {
     o->debug_store_z = 0;
     o->use_graph = 1;
     o->multi_chain_z = 1;
+    o->autotune = 0;
 }
 
 int64_t hsp_max_p(void) { return kMaxP; }
@@ -555,7 +939,7 @@ hsp_status hsp_create(const float* X, const uint8_t* y, int64_t N, int64_t p,
         delete s;
         return fail(nullptr, HSP_EINVAL, "thin must be >= 1 and max_draws in [1, 2^30]");
     }
-    hsp_status st = create_impl(s, X, y, N, p);
+    hsp_status st = s->opt.x_stream ? create_stream_impl(s, X, y, N, p) : create_impl(s, X, y, N, p);
     if (st != HSP_OK) {
         if (!s->err.empty()) g_create_error = s->err;
         free_state(s);
@@ -598,14 +982,20 @@ struct hsp_batch {
     bool timing = false;
     EventTimer timer;  // timed batched sweeps
     std::string err;
+    // launch-shape parameters of the packs (the autotuner may change them)
+    uint32_t mc_gz = 0;        // blocks of each multi-chain z pass (0: two per compute unit)
+    uint32_t bw_pct = 100;     // pack split model: z-pass bandwidth per block, percent of nominal
+    bool autotune = false;
+    std::string plan_note = "built-in";
 };
 
 namespace {
 
-void free_batch(hsp_batch* b) {
-    if (!b) return;
+// Release the packs' device buffers and the captured graph.
+void free_packs(hsp_batch* b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
     for (Pack& pk : b->packs) {
         if (pk.dmc) (void)hipFree(pk.dmc);
         if (pk.mc_partial) (void)hipFree(pk.mc_partial);
@@ -616,6 +1006,12 @@ void free_batch(hsp_batch* b) {
         for (uint32_t* q : pk.sched)
             if (q) (void)hipFree(q);
     }
+    b->packs.clear();
+}
+
+void free_batch(hsp_batch* b) {
+    if (!b) return;
+    free_packs(b);
     b->timer.reset();
     for (auto it = b->chains.rbegin(); it != b->chains.rend(); ++it) free_state(*it);  // borrowers first
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -686,7 +1082,8 @@ hsp_status plan_packs(hsp_batch* b) {
                 pk.mc_ld = own->x.ld;
                 // one block per claimed unit at most, two per compute unit
                 const uint32_t units = ((own->x.N + kMcRows - 1) / kMcRows + kMcUnit - 1) / kMcUnit;
-                pk.mc_gz = std::max<uint32_t>(1, std::min<uint32_t>(2u * (uint32_t)num_cus, units));
+                const uint32_t want = b->mc_gz ? b->mc_gz : 2u * (uint32_t)num_cus;
+                pk.mc_gz = std::max<uint32_t>(1, std::min<uint32_t>(want, units));
                 for (size_t j = g0; j < std::min(same.size(), g0 + kMcChains); ++j) {
                     pk.chains.push_back(same[j]);
                     taken[same[j]] = true;
@@ -716,7 +1113,8 @@ hsp_status plan_packs(hsp_batch* b) {
         if (ids.empty()) continue;
         const int cap = pack_capacity(xt, chunks, num_cus);
         if (cap < 2) return batch_fail(b, HSP_EHIP, "no resident capacity for a pack");
-        const double bw = 7.0e6 / cap;  // bytes per microsecond per block (about 7 TB/s in all)
+        // bytes per microsecond per block (about 7 TB/s in all, scaled by the tuner)
+        const double bw = 7.0e6 / cap * (b->bw_pct / 100.0);
         std::vector<ChainCost> cost(b->chains.size());
         const int rows = rows_for_chunks(chunks);
         for (size_t i : ids) {
@@ -786,6 +1184,8 @@ hsp_status plan_packs(hsp_batch* b) {
             SweepArgs h = sweep_args(s, pk.mc ? (kModeSweep & ~kModeZ) | kModeBsum : kModeSweep);
             h.gp = pk.gp[j];
             h.gz = pk.gz[j];
+            h.z_static_pct = kZStaticPctDefault;
+            h.z_unit = kZUnitDefault;
             h.zgroups = (h.gz + kZGroup - 1) / kZGroup;
             h.block0 = blk;
             if (s->x.p > (uint32_t)kSmallP) {
@@ -834,6 +1234,144 @@ hsp_status plan_packs(hsp_batch* b) {
     return HSP_OK;
 }
 
+// The packs (if not planned yet) and the graph of one batched sweep.
+hsp_status batch_build(hsp_batch* b) {
+    if (b->packs.empty()) {
+        hsp_status st = plan_packs(b);
+        if (st != HSP_OK) return st;
+    }
+    if (b->graph) return HSP_OK;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    for (size_t i = 0; !e && i < b->packs.size(); ++i) {
+        const Pack& pk = b->packs[i];
+        if (pk.mc) e = mc_launch(pk.dmc, pk.mc_ld, pk.mc_gz, b->stream);
+        if (!e) e = pack_launch(pk.xtype, pk.chunks, pk.dtab, pk.dmap, pk.blocks, b->stream);
+    }
+    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (!e) e = e2;
+    if (!e) e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e) return batch_fail(b, HSP_EHIP, std::string("batch graph capture: ") + hipGetErrorString(e));
+    return HSP_OK;
+}
+
+// Cache key of a batch: the device and a hash of every chain's design.
+std::string batch_tune_key(const hsp_batch* b) {
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the batch's description
+    auto mix = [&](uint64_t v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (v >> (8 * i)) & 0xFFu;
+            h *= 1099511628211ull;
+        }
+    };
+    mix((uint64_t)b->chains[0]->opt.multi_chain_z);
+    for (size_t i = 0; i < b->chains.size(); ++i) {
+        const hsp_state* s = b->chains[i];
+        mix(s->x.N);
+        mix(s->x.p);
+        mix((uint64_t)s->x.xtype);
+        size_t own = i;
+        for (size_t j = 0; j < b->chains.size(); ++j)
+            if (b->chains[j] == (s->owner ? s->owner : s)) own = j;
+        mix(own);
+    }
+    char hex[17];
+    std::snprintf(hex, sizeof hex, "%016llx", (unsigned long long)h);
+    const hsp_state* s0 = b->chains[0];
+    return "batch-v1 " + device_tag(s0->device, s0->num_cus) + " chains=" + std::to_string(b->chains.size()) +
+           " h=" + hex;
+}
+
+// Mean milliseconds of `timed` replays of the batch's graph after `warm`.
+hsp_status time_batch(hsp_batch* b, int warm, int timed, double* ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return batch_fail(b, HSP_EHIP, "event");
+    hipError_t e = hipEventCreate(&e1);
+    for (int i = 0; !e && i < warm; ++i) e = hipGraphLaunch(b->graph, b->stream);
+    if (!e) e = hipEventRecord(e0, b->stream);
+    for (int i = 0; !e && i < timed; ++i) e = hipGraphLaunch(b->graph, b->stream);
+    if (!e) e = hipEventRecord(e1, b->stream);
+    if (!e) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (!e) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e) return batch_fail(b, HSP_EHIP, std::string("timing a batched sweep: ") + hipGetErrorString(e));
+    *ms = (double)t / timed;
+    for (size_t i = 0; i < b->chains.size(); ++i) {
+        hsp_status st = check_device_flags(b->chains[i]);
+        if (st != HSP_OK) return batch_fail(b, st, "chain " + std::to_string(i) + ": " + b->chains[i]->err);
+    }
+    return HSP_OK;
+}
+
+// The autotuner for a batch: blocks of each multi-chain z pass and the
+// bandwidth the pack split model gives a z-pass block, by timing a few
+// batched sweeps of every candidate (or from the cache).  Every chain's
+// state is put back afterwards.
+hsp_status batch_tune(hsp_batch* b) {
+    const std::string key = batch_tune_key(b);
+    const char* path = tune_cache_path();
+    std::string cached;
+    long mcg = 0, bwp = 0;
+    if (path && tune_cache_get(path, key, &cached) && tune_parse(cached, "mc_gz", &mcg) &&
+        tune_parse(cached, "bw", &bwp) && mcg >= 0 && mcg <= 65536 && bwp >= 10 && bwp <= 1000) {
+        b->mc_gz = (uint32_t)mcg;
+        b->bw_pct = (uint32_t)bwp;
+        b->plan_note = "mc_gz=" + std::to_string(mcg) + " bw=" + std::to_string(bwp) + " (cache)";
+        return HSP_OK;
+    }
+    std::vector<SavedChain> saved(b->chains.size());
+    for (size_t i = 0; i < b->chains.size(); ++i) {
+        hsp_status st = save_chain(b->chains[i], &saved[i]);
+        if (st) return batch_fail(b, st, b->chains[i]->err);
+    }
+    // is there a multi-chain pass to size?
+    hsp_status st = plan_packs(b);
+    if (st) return st;
+    uint32_t units = 0;
+    for (const Pack& pk : b->packs)
+        if (pk.mc) {
+            const hsp_state* own = b->chains[pk.chains[0]];
+            units = std::max(units, ((own->x.N + kMcRows - 1) / kMcRows + kMcUnit - 1) / kMcUnit);
+        }
+    free_packs(b);
+    const uint32_t cus = (uint32_t)b->chains[0]->num_cus;
+    std::vector<uint32_t> mcs{0};
+    if (units)
+        for (uint32_t m : {cus / 2, cus, 3 * cus / 2, 2 * cus, 3 * cus})
+            if (m >= 1 && m <= units && std::find(mcs.begin(), mcs.end(), m) == mcs.end()) mcs.push_back(m);
+    double best_ms = 1e300;
+    uint32_t best_mc = 0, best_bw = 100;
+    for (uint32_t mc : mcs)
+        for (uint32_t bw : {60u, 100u, 160u}) {
+            b->mc_gz = mc;
+            b->bw_pct = bw;
+            st = batch_build(b);
+            double ms = 0.0;
+            if (!st) st = time_batch(b, 1, 3, &ms);
+            free_packs(b);
+            if (st) return st;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_mc = mc;
+                best_bw = bw;
+            }
+        }
+    b->mc_gz = best_mc;
+    b->bw_pct = best_bw;
+    for (size_t i = 0; i < b->chains.size(); ++i) {
+        st = restore_chain(b->chains[i], saved[i]);
+        if (st) return batch_fail(b, st, b->chains[i]->err);
+    }
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "mc_gz=%u bw=%u ms=%.4f", best_mc, best_bw, best_ms);
+    b->plan_note = std::string(buf) + " (measured)";
+    if (path) (void)tune_cache_put(path, key, buf);
+    return HSP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -872,6 +1410,8 @@ hsp_status hsp_batch_create(const hsp_dataset* ds, int32_t n_ds, const int32_t* 
             o.x_type = ds[d].x_type;
             o.chain_id = chain_id;
             o.use_graph = 1;
+            o.autotune = 0;  // the batch tunes its packs instead
+            o.x_stream = 0;  // every dataset of a batch is resident
             hsp_state* s = nullptr;
             hsp_status st;
             if (c == 0) {
@@ -899,6 +1439,7 @@ hsp_status hsp_batch_create(const hsp_dataset* ds, int32_t n_ds, const int32_t* 
             b->chains.push_back(s);
         }
     }
+    b->autotune = base.autotune != 0;
     *out = b;
     return HSP_OK;
 }
@@ -921,22 +1462,13 @@ hsp_status hsp_batch_sweep(hsp_batch* b, int64_t n) {
             return batch_fail(b, HSP_EINVAL, "the sweep counter would exceed 2^32");
     }
     if (!b->graph) {
-        if (b->packs.empty()) {
-            hsp_status st = plan_packs(b);
+        if (b->autotune) {
+            b->autotune = false;  // once per batch
+            hsp_status st = batch_tune(b);
             if (st != HSP_OK) return st;
         }
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-        for (size_t i = 0; !e && i < b->packs.size(); ++i) {
-            const Pack& pk = b->packs[i];
-            if (pk.mc) e = mc_launch(pk.dmc, pk.mc_ld, pk.mc_gz, b->stream);
-            if (!e) e = pack_launch(pk.xtype, pk.chunks, pk.dtab, pk.dmap, pk.blocks, b->stream);
-        }
-        hipError_t e2 = hipStreamEndCapture(b->stream, &g);
-        if (!e) e = e2;
-        if (!e) e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-        if (g) (void)hipGraphDestroy(g);
-        if (e) return batch_fail(b, HSP_EHIP, std::string("batch graph capture: ") + hipGetErrorString(e));
+        hsp_status st = batch_build(b);
+        if (st != HSP_OK) return st;
     }
     for (int64_t i = 0; i < n; ++i) {
         if (b->timing && b->timer.begin(b->stream) != hipSuccess)
@@ -994,6 +1526,16 @@ hsp_status hsp_sweep(hsp_state* s, int64_t n) {
     if (n < 0) return fail(s, HSP_EINVAL, "n_iter must be >= 0");
     if (s->sweeps_done + (uint64_t)n >= (uint64_t(1) << 32) - 1)
         return fail(s, HSP_EINVAL, "the sweep counter would exceed 2^32");
+    if (s->streamed) {
+        for (int64_t i = 0; i < n; ++i) {
+            if (s->timing) HIP_TRY(s->timer.begin(s->stream));
+            hsp_status st = enqueue_stream(s, kModeSweep);
+            if (st) return st;
+            if (s->timing) HIP_TRY(s->timer.end(s->stream));
+        }
+        s->sweeps_done += (uint64_t)n;
+        return HSP_OK;
+    }
     if (s->opt.use_graph && !s->graph) {
         hipError_t e = capture(s, &s->graph);
         if (e) return fail_hip(s, "graph capture", e);
@@ -1101,10 +1643,15 @@ hsp_status hsp_step(hsp_state* s, uint32_t which) {
     if (which & HSP_STEP_BETA) mode |= kModeBeta;
     if (which & HSP_STEP_NUXI) mode |= kModeNuXi;
     if (which & HSP_STEP_ADVANCE) mode |= kModeAdvance;
-    SweepArgs h;
     HIP_TRY(hipStreamSynchronize(s->stream));
-    HIP_TRY(put_args(s, mode, 1, &h));
-    HIP_TRY(sweep_launch(h, s->dtab + 1, s->plan, s->stream));
+    if (s->streamed) {
+        hsp_status st = enqueue_stream(s, mode);
+        if (st) return st;
+    } else {
+        SweepArgs h;
+        HIP_TRY(put_args(s, mode, 1, &h));
+        HIP_TRY(sweep_launch(h, s->dtab + 1, s->plan, s->stream));
+    }
     hsp_status st = sync_state(s);
     if (st) return st;
     if (which & HSP_STEP_ADVANCE) {
@@ -1173,6 +1720,7 @@ hsp_status hsp_get_timing(hsp_state* s, double* zpass_ms, double* sweep_ms, int6
 hsp_status hsp_set_phase_trace(hsp_state* s, int32_t enable) {
     if (!s) return HSP_EINVAL;
     HIP_TRY(hipStreamSynchronize(s->stream));
+    s->sd_mode = 0;  // streamed launch descriptions carry the trace pointer
     if (s->graph) {
         (void)hipGraphExecDestroy(s->graph);
         s->graph = nullptr;
@@ -1246,6 +1794,50 @@ hsp_status hsp_gram(const void* X, int32_t x_type, int64_t N, int64_t p, int64_t
     return HSP_OK;
 }
 
+hsp_status hsp_get_plan(hsp_state* s, int64_t* group_blocks, int64_t* z_blocks, int64_t* static_pct,
+                        int64_t* unit, char* note, int64_t note_cap) {
+    if (!s) return HSP_EINVAL;
+    if (group_blocks) *group_blocks = s->plan.gp;
+    if (z_blocks) *z_blocks = s->plan.gz;
+    if (static_pct) *static_pct = s->plan.static_pct;
+    if (unit) *unit = s->plan.unit;
+    if (note && note_cap > 0) std::snprintf(note, (size_t)note_cap, "%s", s->plan_note.c_str());
+    return HSP_OK;
+}
+
+hsp_status hsp_batch_get_plan(hsp_batch* b, int64_t* mc_blocks, int64_t* bw_pct, int64_t* packs, char* note,
+                              int64_t note_cap) {
+    if (!b) return HSP_EINVAL;
+    if (mc_blocks) *mc_blocks = b->mc_gz;
+    if (bw_pct) *bw_pct = b->bw_pct;
+    if (packs) *packs = (int64_t)b->packs.size();
+    if (note && note_cap > 0) std::snprintf(note, (size_t)note_cap, "%s", b->plan_note.c_str());
+    return HSP_OK;
+}
+
+hsp_status hsp_tune_key(hsp_state* s, char* key, int64_t cap) {
+    if (!s || !key || cap < 1) return HSP_EINVAL;
+    const std::string k = sweep_tune_key(s);
+    if ((int64_t)k.size() >= cap) return fail(s, HSP_EINVAL, "key buffer too small");
+    std::memcpy(key, k.c_str(), k.size() + 1);
+    return HSP_OK;
+}
+
+hsp_status hsp_tune_cache_put(const char* path, const char* key, const char* value) {
+    if (!path || !key || !value) return fail(nullptr, HSP_EINVAL, "NULL argument");
+    if (!tune_cache_put(path, key, value)) return fail(nullptr, HSP_EINVAL, "cache write failed or bad key/value");
+    return HSP_OK;
+}
+
+hsp_status hsp_tune_cache_get(const char* path, const char* key, char* value, int64_t cap) {
+    if (!path || !key || !value || cap < 1) return fail(nullptr, HSP_EINVAL, "bad arguments");
+    std::string v;
+    if (!tune_cache_get(path, key, &v)) return fail(nullptr, HSP_ERANGE, "no cache entry");
+    if ((int64_t)v.size() >= cap) return fail(nullptr, HSP_EINVAL, "value buffer too small");
+    std::memcpy(value, v.c_str(), v.size() + 1);
+    return HSP_OK;
+}
+
 hsp_status hsp_philox(uint64_t seed, const uint32_t* ctr, int64_t n, uint32_t* out) {
     hsp_state* s = nullptr;
     if (!ctr || !out || n < 0 || n > (int64_t(1) << 28)) return fail(nullptr, HSP_EINVAL, "bad arguments");
@@ -1268,6 +1860,34 @@ hsp_status hsp_read_ceiling(hsp_state* s, int32_t iters, double* ms_per_pass, do
     if (s->poisoned) return HSP_EPOISONED;
     const size_t esz = s->x.xtype == 0 ? 4 : 2;
     const size_t bytes = (size_t)s->x.N * s->x.ld * esz;
+    if (s->streamed) {
+        // the link a streamed sweep is bound by: X copied from the pinned
+        // host buffer into the device chunk buffers, chunk by chunk
+        const size_t row_bytes = (size_t)s->x.ld * esz;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        HIP_TRY(hipEventCreate(&e0));
+        hipError_t e = hipEventCreate(&e1);
+        for (int i = -1; !e && i < iters; ++i) {
+            if (i == 0) e = hipEventRecord(e0, s->stream);
+            for (uint32_t c = 0; !e && c < s->nchunks; ++c) {
+                const size_t r0 = (size_t)c * s->chunk_rows;
+                const size_t rows = std::min<size_t>(s->chunk_rows, s->x.N - r0);
+                e = hipMemcpyAsync(s->stage[c & 1], static_cast<const char*>(s->Xhost) + r0 * row_bytes,
+                                   rows * row_bytes, hipMemcpyHostToDevice, s->stream);
+            }
+        }
+        if (!e) e = hipEventRecord(e1, s->stream);
+        if (!e) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (!e) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        HIP_TRY(e);
+        *ms_per_pass = ms / iters;
+        if (bytes_per_pass) *bytes_per_pass = (double)bytes;
+        return HSP_OK;
+    }
     float* sink = nullptr;
     HIP_TRY(dalloc(&sink, 1));
     hipEvent_t e0 = nullptr, e1 = nullptr;

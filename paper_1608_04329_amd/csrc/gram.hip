@@ -86,9 +86,11 @@ __device__ __forceinline__ void pair_of(uint32_t pair, uint32_t nt, uint32_t& ti
     tj = r + idx;
 }
 
-// Pairs [pair0, pair0 + gridDim.x); work holds gridDim.y x gridDim.x tiles.
+// Pairs [pair0, pair0 + gridDim.x) over the row splits of x, which are the
+// splits split0, split0 + 1, ... of the whole design (x may be a chunk of its
+// rows); work holds gridDim.x tiles per split, split-major.
 __global__ __launch_bounds__(256) void gram_tile_kernel(XLayout x, double* __restrict__ work, uint32_t nt,
-                                                        uint32_t pair0, uint32_t rows_per_split) {
+                                                        uint32_t pair0, uint32_t rows_per_split, uint32_t split0) {
     __shared__ double S[kGT][kGT + 2];
     __shared__ double T[kGT][kGT + 2];
     uint32_t ti, tj;
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(256) void gram_tile_kernel(XLayout x, double* __res
             acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
     }
-    double* out = work + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (kGT * kGT);
+    double* out = work + ((size_t)(split0 + blockIdx.y) * gridDim.x + blockIdx.x) * (kGT * kGT);
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -190,7 +192,7 @@ __global__ void pad_gram_kernel(const double* __restrict__ G, uint32_t p, uint32
 
 }  // namespace
 
-GramGeometry gram_geometry(const XLayout& x, int num_cus) {
+GramGeometry gram_geometry(const XLayout& x, int num_cus, uint64_t max_rows_per_split) {
     GramGeometry g;
     g.nt = (x.p + kGT - 1) / kGT;
     g.npairs = g.nt * (g.nt + 1) / 2;
@@ -201,6 +203,7 @@ GramGeometry gram_geometry(const XLayout& x, int num_cus) {
     if (ns < 1) ns = 1;
     uint64_t rps = (x.N + ns - 1) / ns;
     rps = (rps + kGT - 1) / kGT * kGT;
+    if (max_rows_per_split >= (uint64_t)kGT && rps > max_rows_per_split) rps = max_rows_per_split / kGT * kGT;
     g.nsplit = (uint32_t)((x.N + rps - 1) / rps);
     g.rows_per_split = (uint32_t)rps;
     return g;
@@ -220,7 +223,7 @@ hipError_t gram_launch_chunked(const XLayout& x, const int32_t* e, double* G, do
     for (uint32_t pair0 = 0; pair0 < g.npairs; pair0 += (uint32_t)chunk) {
         const uint32_t npc = (uint32_t)std::min<size_t>(chunk, g.npairs - pair0);
         hipLaunchKernelGGL(gram_tile_kernel, dim3(npc, g.nsplit), dim3(256), 0, st, x, work, g.nt, pair0,
-                           g.rows_per_split);
+                           g.rows_per_split, 0u);
         const size_t n = (size_t)npc * kGT * kGT;
         hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                            (const double*)work, g.nsplit, npc, pair0, g.nt, x.p, e, G);
@@ -233,6 +236,24 @@ hipError_t gram_launch_chunked(const XLayout& x, const int32_t* e, double* G, do
 hipError_t gram_launch(const XLayout& x, const int32_t* e, double* G, double* work, int num_cus,
                        hipStream_t st) {
     return gram_launch_chunked(x, e, G, work, gram_work_doubles(x, num_cus), num_cus, st);
+}
+
+hipError_t gram_chunk_launch(const XLayout& chunk, const GramGeometry& g, uint32_t split0, double* work,
+                             hipStream_t st) {
+    const uint32_t ns = (chunk.N + g.rows_per_split - 1) / g.rows_per_split;
+    if (ns == 0) return hipSuccess;
+    if (split0 + ns > g.nsplit) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gram_tile_kernel, dim3(g.npairs, ns), dim3(256), 0, st, chunk, work, g.nt, 0u,
+                       g.rows_per_split, split0);
+    return hipGetLastError();
+}
+
+hipError_t gram_reduce_launch(const double* work, const GramGeometry& g, uint32_t p, const int32_t* e, double* G,
+                              hipStream_t st) {
+    const size_t n = (size_t)g.npairs * kGT * kGT;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, work, g.nsplit,
+                       g.npairs, 0u, g.nt, p, e, G);
+    return hipGetLastError();
 }
 
 hipError_t pad_gram_launch(const double* G, uint32_t p, uint32_t P, double* Gp, hipStream_t st) {

@@ -45,17 +45,16 @@ constexpr int kSmallP = 16;            // p up to this runs the one-block p-side
 #endif
 constexpr int kMaxGroup = HSP_MAX_GROUP;  // most blocks of the p-side group
 constexpr int kZGroup = 16;            // z-pass blocks whose partials one block sums
-#ifndef HSP_Z_STATIC_PCT
-#define HSP_Z_STATIC_PCT 40
-#endif
-#ifndef HSP_Z_UNIT
-#define HSP_Z_UNIT 8
-#endif
 // Rows per wave tile of the z pass for rows of kc 16-byte chunks per lane
 // (the register budget: taller tiles for kc <= 2 spill).
 constexpr int rows_for_chunks(int kc) { return kc <= 4 ? 8 : (kc <= 8 ? 4 : 2); }
-constexpr int kZStaticPct = HSP_Z_STATIC_PCT;  // share of the z-pass tiles dealt out statically
-constexpr int kZUnit = HSP_Z_UNIT;             // tiles per claimed unit of the remainder
+// How the z pass deals out its row tiles (a launch parameter; the autotuner
+// may pick others): this share in percent statically, interleaved over all
+// waves, the rest in units of this many tiles to whichever block asks next.
+// Neither changes any result (X^T z is exact in any split of the rows).
+constexpr uint32_t kZStaticPctDefault = 40;
+constexpr uint32_t kZUnitDefault = 8;
+constexpr uint32_t kZUnitMax = 64;
 // LDS of one sweep-kernel block: two 64 x 66 float64 tiles (67,584 bytes; rows
 // 16-byte aligned).  The same buffer holds the z pass's reduction segment and
 // the packed Q of the one-block path (p (p + 1) / 2 <= 8256 doubles).
@@ -77,6 +76,7 @@ struct Ctrl {
     alignas(128) unsigned long long z_count;    // z-pass groups finished (monotonic)
     alignas(128) uint32_t task_next;  // next factorisation task of the shared queue (zero between launches)
     alignas(128) uint32_t z_next;     // next z-pass unit of the shared remainder (zero between launches)
+    alignas(128) uint32_t z_done;     // z groups finished in a launch without a p-side (zero between launches)
 };
 
 enum : uint32_t {
@@ -154,6 +154,10 @@ struct SweepArgs {
     HSP_GLOBAL const uint32_t* tasks;   // tile path: every group block's task list, concatenated
     HSP_GLOBAL const uint32_t* task_off;  // gp + 1 offsets into tasks
     HSP_GLOBAL uint32_t* ver;           // tile path: 2 x nt x nt tile version counters (zero between launches)
+    uint32_t z_static_pct;   // z pass: share of the row tiles dealt out statically (0..100)
+    uint32_t z_unit;         // z pass: tiles per claimed unit of the rest (1..kZUnitMax)
+    uint32_t first_row;      // global index of x.X's first row (X streamed in row chunks; else 0):
+                             // y, the Philox counters and the debug outputs use global rows
 };
 
 // Device view of a launch description.
@@ -214,10 +218,17 @@ struct SweepPlan {
     int chunks;    // 16-byte vectors per lane per row
     int rows;      // rows per wave tile
     int capacity;  // resident blocks of the chosen kernel on the device
+    uint32_t static_pct = kZStaticPctDefault;
+    uint32_t unit = kZUnitDefault;
 };
 
-// Plan a launch for X's shape; num_cus from the device.
-hipError_t sweep_plan(const XLayout& x, int num_cus, SweepPlan* plan);
+// Plan a launch for X's shape; num_cus from the device.  gp_req > 0 asks for
+// a p-side group of that many blocks (clamped to what the shape can use);
+// the z pass gets the rest of the resident capacity, up to one block per
+// four row tiles.
+hipError_t sweep_plan(const XLayout& x, int num_cus, SweepPlan* plan, uint32_t gp_req = 0);
+// Largest p-side group a shape can use on a device of this capacity.
+uint32_t max_group(const XLayout& x, int capacity);
 // Fill gp, gz and zgroups of a launch description from the plan and its mode.
 void sweep_finish_args(SweepArgs* a, const SweepPlan& plan);
 // Enqueue one launch of the sweep kernel for one chain: table is a device
@@ -242,7 +253,19 @@ hipError_t mc_launch(const McArgs* mc, uint32_t ld, uint32_t gz, hipStream_t st)
 struct GramGeometry {
     uint32_t nt, npairs, nsplit, rows_per_split;
 };
-GramGeometry gram_geometry(const XLayout& x, int num_cus);
+// max_rows_per_split > 0 caps the rows of a split (more splits), so that a
+// design streamed in chunks of whole splits can form its partials chunk by chunk.
+GramGeometry gram_geometry(const XLayout& x, int num_cus, uint64_t max_rows_per_split = 0);
+// The partial tiles of every tile pair over the splits of one chunk of rows
+// (chunk.N rows, the splits split0, split0 + 1, ... of geometry g, chunk.N a
+// multiple of g.rows_per_split except for the last chunk) into work, which
+// holds g.nsplit x g.npairs tiles; then G from all of them, summed in split
+// order exactly as gram_launch sums them (the same G, bit for bit, when g is
+// the same geometry).
+hipError_t gram_chunk_launch(const XLayout& chunk, const GramGeometry& g, uint32_t split0, double* work,
+                             hipStream_t st);
+hipError_t gram_reduce_launch(const double* work, const GramGeometry& g, uint32_t p, const int32_t* e, double* G,
+                              hipStream_t st);
 // Doubles of workspace that hold every partial tile at once.
 size_t gram_work_doubles(const XLayout& x, int num_cus);
 // work must hold gram_work_doubles(x) doubles.

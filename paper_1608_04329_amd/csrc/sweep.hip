@@ -71,7 +71,15 @@ KernelFn kernel_for(int xtype, int chunks) {
 
 }  // namespace
 
-hipError_t sweep_plan(const XLayout& x, int num_cus, SweepPlan* plan) {
+uint32_t max_group(const XLayout& x, int capacity) {
+    const uint32_t nt = (x.p + kTile - 1) / kTile;
+    uint32_t gp = x.p <= (uint32_t)kSmallP ? 1u : nt * (nt + 1) / 2;
+    if (gp > (uint32_t)kMaxGroup) gp = kMaxGroup;
+    if (gp > (uint32_t)capacity / 4) gp = capacity / 4 > 0 ? capacity / 4 : 1;
+    return gp;
+}
+
+hipError_t sweep_plan(const XLayout& x, int num_cus, SweepPlan* plan, uint32_t gp_req) {
     const int vec = x.xtype == 0 ? 4 : 8;
     plan->chunks = (int)((x.ld + kWave * vec - 1) / (kWave * vec));
     plan->rows = rows_for_chunks(plan->chunks);
@@ -83,10 +91,8 @@ hipError_t sweep_plan(const XLayout& x, int num_cus, SweepPlan* plan) {
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     plan->capacity = per_cu * num_cus;
-    const uint32_t nt = (x.p + kTile - 1) / kTile;
-    uint32_t gp = x.p <= (uint32_t)kSmallP ? 1u : nt * (nt + 1) / 2;
-    if (gp > (uint32_t)kMaxGroup) gp = kMaxGroup;
-    if (gp > (uint32_t)plan->capacity / 4) gp = plan->capacity / 4 > 0 ? plan->capacity / 4 : 1;
+    uint32_t gp = max_group(x, plan->capacity);
+    if (gp_req > 0 && gp_req < gp) gp = gp_req;
     plan->gp = gp;
     const uint64_t tiles = (x.N + plan->rows - 1) / plan->rows;
     uint64_t gz = (tiles + kWPB - 1) / kWPB;
@@ -101,6 +107,8 @@ void sweep_finish_args(SweepArgs* a, const SweepPlan& plan) {
     a->gp = plan.gp;
     a->gz = (a->mode & kModeZ) ? plan.gz : 0u;
     a->zgroups = (a->gz + kZGroup - 1) / kZGroup;
+    a->z_static_pct = plan.static_pct;
+    a->z_unit = plan.unit;
 }
 
 hipError_t sweep_launch(const SweepArgs& host, const SweepArgs* const* table, const SweepPlan& plan,

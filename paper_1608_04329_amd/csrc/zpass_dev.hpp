@@ -161,10 +161,12 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
 #pragma unroll
         for (int r = 1; r < R; ++r) eta = (lane == r) ? s[r] : eta;
 
-        // lane r < R draws z for row row0 + r
+        // lane r < R draws z for row row0 + r (global row first_row + row0 + r
+        // when X arrives in row chunks)
         const uint32_t row = row0 + (uint32_t)lane;
         const bool active = lane < R && row < N;
-        const float ys = (active && a.y[row]) ? 1.0f : -1.0f;
+        const uint32_t grow = a.first_row + row;
+        const float ys = (active && a.y[grow]) ? 1.0f : -1.0f;
         const float mu = ys * eta;
         const bool gauss = mu > 0.47f;
         const float den = sqrtf(fmaf(mu, mu, 4.0f)) - mu;  // 2 theta
@@ -175,7 +177,7 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
         bool done = !active;
         for (uint32_t round = 0; __ballot(!done) != 0ull; ++round) {
             if (!done) {
-                const Words4 w = draw_words(a.seed, row, ksweep, kTagZ, round, a.chain);
+                const Words4 w = draw_words(a.seed, grow, ksweep, kTagZ, round, a.chain);
                 float t0, t1;
                 bool a0, a1;
                 tn_candidate(mu, gauss, theta, inv_theta, u01f(w.w0), u01f(w.w1), t0, a0);
@@ -198,8 +200,8 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
         if (active) {
             maxatt = max(maxatt, (uint32_t)(att + 1));
             if (a.zdbg) {
-                a.zdbg[row] = zval;
-                a.adbg[row] = att | (gauss ? (1 << 30) : 0);
+                a.zdbg[grow] = zval;
+                a.adbg[grow] = att | (gauss ? (1 << 30) : 0);
             }
         }
 
@@ -219,14 +221,15 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
             }
     };
 
-    // Most tiles are dealt out statically, interleaved over all waves; the
-    // rest go out in units of kZUnit tiles to whichever block asks next, so
-    // blocks on busier CUs do less of them.  Thread 0 reserves the next unit
-    // before working on the current one.
-    const uint32_t n_static = (uint32_t)((uint64_t)n_tiles * kZStaticPct / 100 / W * W);
+    // A share of the tiles is dealt out statically, interleaved over all
+    // waves; the rest go out in units of z_unit tiles to whichever block asks
+    // next, so blocks on busier CUs do less of them.  Thread 0 reserves the
+    // next unit before working on the current one.
+    const uint32_t unit = a.z_unit;
+    const uint32_t n_static = (uint32_t)((uint64_t)n_tiles * a.z_static_pct / 100 / W * W);
     for (uint32_t t = zrank * kWPB + wave; t < n_static; t += W) tile(t);
     if (n_static < n_tiles) {
-        const uint32_t n_units = (n_tiles - n_static + kZUnit - 1) / kZUnit;
+        const uint32_t n_units = (n_tiles - n_static + unit - 1) / unit;
         double* slot = red;  // free until the reduction below
         if (threadIdx.x == 0) *slot = (double)atomicAdd(&a.ctrl->z_next, 1u);
         __syncthreads();
@@ -235,8 +238,8 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
         while (u < n_units) {
             uint32_t next = 0;
             if (threadIdx.x == 0) next = atomicAdd(&a.ctrl->z_next, 1u);
-            for (uint32_t j = wave; j < (uint32_t)kZUnit; j += kWPB) {
-                const uint32_t t = n_static + u * kZUnit + j;
+            for (uint32_t j = wave; j < unit; j += kWPB) {
+                const uint32_t t = n_static + u * unit + j;
                 if (t < n_tiles) tile(t);
             }
             if (threadIdx.x == 0) *slot = (double)next;
@@ -312,6 +315,13 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
             // every block of the group has arrived
             __hip_atomic_store(&a.zgrp_count[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             atomicAdd(&a.ctrl->z_count, 1ull);
+            // a launch without a p-side group (a chunk of rows) resets the
+            // shared unit counter itself once every group has finished, i.e.
+            // every block has left its claim loop
+            if (a.gp == 0 && atomicAdd(&a.ctrl->z_done, 1u) == a.zgroups - 1) {
+                __hip_atomic_store(&a.ctrl->z_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&a.ctrl->z_next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
 }

@@ -29,14 +29,16 @@ EXPORTS = ["hsp_default_options", "hsp_max_p", "hsp_gram", "hsp_create", "hsp_sw
            "hsp_get_timing", "hsp_philox", "hsp_set_phase_trace", "hsp_get_phase_trace",
            "hsp_tile_schedule", "hsp_read_ceiling", "hsp_batch_create", "hsp_batch_size",
            "hsp_batch_chain", "hsp_batch_sweep", "hsp_batch_sync", "hsp_batch_set_timing",
-           "hsp_batch_get_timing", "hsp_batch_last_error", "hsp_batch_destroy"]
+           "hsp_batch_get_timing", "hsp_batch_last_error", "hsp_batch_destroy", "hsp_get_plan",
+           "hsp_batch_get_plan", "hsp_tune_key", "hsp_tune_cache_put", "hsp_tune_cache_get"]
 
 
 class hsp_options(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("chain_id", C.c_uint32), ("x_type", C.c_int32),
                 ("x_on_host", C.c_int32), ("record_lambda", C.c_int32), ("thin", C.c_int64),
                 ("max_draws", C.c_int64), ("hip_stream", C.c_void_p), ("debug_store_z", C.c_int32),
-                ("use_graph", C.c_int32), ("multi_chain_z", C.c_int32)]
+                ("use_graph", C.c_int32), ("multi_chain_z", C.c_int32), ("autotune", C.c_int32),
+                ("x_stream", C.c_int32), ("stream_rows", C.c_int64)]
 
 
 class hsp_dataset(C.Structure):
@@ -105,6 +107,14 @@ def load():
     L.hsp_batch_get_timing.restype = st
     L.hsp_batch_last_error.argtypes = [vp]; L.hsp_batch_last_error.restype = C.c_char_p
     L.hsp_batch_destroy.argtypes = [vp]; L.hsp_batch_destroy.restype = st
+    pi64 = C.POINTER(i64)
+    L.hsp_get_plan.argtypes = [vp, pi64, pi64, pi64, pi64, C.c_char_p, i64]; L.hsp_get_plan.restype = st
+    L.hsp_batch_get_plan.argtypes = [vp, pi64, pi64, pi64, C.c_char_p, i64]
+    L.hsp_batch_get_plan.restype = st
+    L.hsp_tune_key.argtypes = [vp, C.c_char_p, i64]; L.hsp_tune_key.restype = st
+    L.hsp_tune_cache_put.argtypes = [C.c_char_p, C.c_char_p, C.c_char_p]; L.hsp_tune_cache_put.restype = st
+    L.hsp_tune_cache_get.argtypes = [C.c_char_p, C.c_char_p, C.c_char_p, i64]
+    L.hsp_tune_cache_get.restype = st
     _lib = L
     return L
 
@@ -303,6 +313,42 @@ def hsp_get_phase_trace(h):
     return out, tpu.value
 
 
+def hsp_get_plan(h):
+    """(group_blocks, z_blocks, static_pct, unit, note) of a state's launch plan."""
+    v = [C.c_int64() for _ in range(4)]
+    note = C.create_string_buffer(256)
+    _check(load().hsp_get_plan(h, *[C.byref(x) for x in v], note, 256), h)
+    return tuple(x.value for x in v) + (note.value.decode(),)
+
+
+def hsp_batch_get_plan(b):
+    """(mc_blocks, bw_pct, packs, note) of a batch's pack shapes."""
+    v = [C.c_int64() for _ in range(3)]
+    note = C.create_string_buffer(256)
+    _check(load().hsp_batch_get_plan(b, *[C.byref(x) for x in v], note, 256))
+    return tuple(x.value for x in v) + (note.value.decode(),)
+
+
+def hsp_tune_key(h):
+    buf = C.create_string_buffer(512)
+    _check(load().hsp_tune_key(h, buf, 512), h)
+    return buf.value.decode()
+
+
+def hsp_tune_cache_put(path, key, value):
+    _check(load().hsp_tune_cache_put(path.encode(), key.encode(), value.encode()))
+
+
+def hsp_tune_cache_get(path, key):
+    """The cached value of key, or None."""
+    buf = C.create_string_buffer(4096)
+    code = load().hsp_tune_cache_get(path.encode(), key.encode(), buf, 4096)
+    if code == HSP_ERANGE:
+        return None
+    _check(code)
+    return buf.value.decode()
+
+
 # ---- convenience wrapper --------------------------------------------------------
 class Sampler:
     """One Horseshoe Probit chain on the GPU.
@@ -312,9 +358,13 @@ class Sampler:
     """
 
     def __init__(self, X, y, seed=1, chain_id=0, x_type="f32", record_lambda=False, thin=1,
-                 max_draws=1024, debug_store_z=False, use_graph=True, stream=None):
+                 max_draws=1024, debug_store_z=False, use_graph=True, stream=None, autotune=False,
+                 x_stream=False, stream_rows=0):
         load()
         opt = hsp_default_options()
+        opt.autotune = int(autotune)
+        opt.x_stream = int(x_stream)
+        opt.stream_rows = int(stream_rows)
         opt.seed = seed
         opt.chain_id = chain_id
         opt.x_type = {"f32": HSP_X_F32, "bf16": HSP_X_BF16}[x_type]
@@ -400,6 +450,9 @@ class Sampler:
     def timing(self):
         return hsp_get_timing(self.h)
 
+    def plan(self):
+        return hsp_get_plan(self.h)
+
 
 class Batch:
     """Many independent chains, advanced together by one graph replay per sweep.
@@ -412,10 +465,11 @@ class Batch:
     """
 
     def __init__(self, datasets, chains=1, seed=1, chain_id=0, record_lambda=False, thin=1,
-                 max_draws=1024, debug_store_z=False, stream=None, multi_chain_z=True):
+                 max_draws=1024, debug_store_z=False, stream=None, multi_chain_z=True, autotune=False):
         load()
         opt = hsp_default_options()
         opt.multi_chain_z = int(multi_chain_z)
+        opt.autotune = int(autotune)
         opt.seed = seed
         opt.chain_id = chain_id
         opt.debug_store_z = int(debug_store_z)
@@ -474,6 +528,9 @@ class Batch:
 
     def timing(self):
         return hsp_batch_get_timing(self.b)
+
+    def plan(self):
+        return hsp_batch_get_plan(self.b)
 
     def close(self):
         if self.b:

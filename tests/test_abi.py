@@ -41,7 +41,7 @@ def test_host_only_entry_points():
     assert hsp.hsp_max_p() >= 1000
     # the options struct has the C layout
     assert o.multi_chain_z == 1
-    assert ctypes.sizeof(hsp.hsp_options) == 64
+    assert ctypes.sizeof(hsp.hsp_options) == 80
 
 
 def test_create_rejects_bad_shapes_before_touching_a_device():
