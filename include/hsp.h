@@ -156,6 +156,22 @@ hsp_status hsp_gram(const void* X, int32_t x_type, int64_t N, int64_t p, int64_t
                     void* hip_stream);
 
 /*
+ * hsp_gram without any allocation, for callers that cannot allocate device
+ * memory (tight serving loops, harnesses that forbid hipMalloc).  Same arguments, same result bit for bit as hsp_gram.  The
+ * partial tiles go to a fixed workspace of 32 MiB compiled into the library
+ * (one per device, held until the process ends) instead of a fresh buffer;
+ * large G are processed in several rounds through it.  Every call on one
+ * device shares that workspace, so calls that overlap in time on one device
+ * (other host threads, or other streams) race and must not be issued.
+ * Runs on hip_stream (NULL: the null stream) and waits for it.
+ * Errors: as hsp_gram; HSP_EINVAL also if a single 64 x 64 tile's partials
+ * (32 KB per row split; at most 1024 splits on a 256-CU device) exceed the
+ * workspace.
+ */
+hsp_status hsp_gram_noalloc(const void* X, int32_t x_type, int64_t N, int64_t p, int64_t ld,
+                            double* G, void* hip_stream);
+
+/*
  * Enqueue n_iter full sweeps on the state's stream and return without
  * waiting.  Sweep k draws, in order: z and lambda^-2 from beta^(k-1), then
  * tau^-2; then beta, nu^-1 and xi^-1 (Section 5, updates (i)-(ii)), and

@@ -1794,6 +1794,27 @@ hsp_status hsp_gram(const void* X, int32_t x_type, int64_t N, int64_t p, int64_t
     return HSP_OK;
 }
 
+hsp_status hsp_gram_noalloc(const void* X, int32_t x_type, int64_t N, int64_t p, int64_t ld, double* G,
+                            void* hip_stream) {
+    hsp_state* s = nullptr;
+    XLayout x{};
+    if (const char* msg = gram_args(X, x_type, N, p, ld, G, &x)) return fail(nullptr, HSP_EINVAL, msg);
+    int num_cus = 0;
+    if (hsp_status st = gram_device(&num_cus)) return st;
+    const size_t need = gram_pair_doubles(x, num_cus);
+    if (need > kGramScratchDoubles)
+        return fail(nullptr, HSP_EINVAL,
+                    "hsp_gram_noalloc: one tile pair needs " + std::to_string(need * 8) +
+                        " bytes of workspace, more than the fixed " + std::to_string(kGramScratchDoubles * 8) +
+                        " bytes");
+    double* work = nullptr;
+    HIP_TRY(gram_scratch(&work));
+    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    HIP_TRY(gram_launch_chunked(x, nullptr, G, work, kGramScratchDoubles, num_cus, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return HSP_OK;
+}
+
 hsp_status hsp_get_plan(hsp_state* s, int64_t* group_blocks, int64_t* z_blocks, int64_t* static_pct,
                         int64_t* unit, char* note, int64_t note_cap) {
     if (!s) return HSP_EINVAL;

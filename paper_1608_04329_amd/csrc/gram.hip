@@ -1,6 +1,8 @@
 // One-time work at creation: the column scales of X, X packed into the
 // library layout, input validation, and G = X^T X in float64 (Section 5,
 // beta step i).  Also the device Philox test hook and the read-ceiling probe.
+#include <mutex>
+
 #include "hsp_internal.hpp"
 #include "philox.hpp"
 
@@ -231,6 +233,39 @@ hipError_t gram_launch_chunked(const XLayout& x, const int32_t* e, double* G, do
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
+}
+
+// A fixed device workspace for callers that cannot allocate: gram_scratch()
+// returns its device address on the current device (found once per device
+// with hipGetSymbolAddress; the array's name is not a device address in host
+// code).  Every call on one device shares it.
+namespace {
+__device__ __align__(256) double scratch[kGramScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t gram_scratch(double** ptr) {
+    *ptr = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+size_t gram_pair_doubles(const XLayout& x, int num_cus) {
+    return (size_t)gram_geometry(x, num_cus).nsplit * kGT * kGT;
 }
 
 hipError_t gram_launch(const XLayout& x, const int32_t* e, double* G, double* work, int num_cus,

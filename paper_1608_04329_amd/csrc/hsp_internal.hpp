@@ -276,6 +276,14 @@ hipError_t gram_launch(const XLayout& x, const int32_t* e, double* G, double* wo
 // nsplit partials, else hipErrorInvalidValue).
 hipError_t gram_launch_chunked(const XLayout& x, const int32_t* e, double* G, double* work,
                                size_t work_doubles, int num_cus, hipStream_t st);
+// Doubles of workspace one 64 x 64 tile pair needs (its partials over every
+// row split); gram_launch_chunked needs at least this much.
+size_t gram_pair_doubles(const XLayout& x, int num_cus);
+// The library's fixed Gram workspace (kGramScratchDoubles doubles, 32 MiB,
+// one per device, held until the process ends): its device address on the
+// current device.  Calls that use it on one device at the same time race.
+constexpr size_t kGramScratchDoubles = (size_t)1 << 22;
+hipError_t gram_scratch(double** ptr);
 // Gp (P x P) = G with an identity block beyond p, zeros elsewhere.
 hipError_t pad_gram_launch(const double* G, uint32_t p, uint32_t P, double* Gp, hipStream_t st);
 

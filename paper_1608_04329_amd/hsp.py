@@ -23,7 +23,7 @@ GAUSS_BIT = 1 << 30
 STATUS_NAMES = {0: "HSP_OK", -1: "HSP_EINVAL", -2: "HSP_ENOMEM", -3: "HSP_EHIP", -4: "HSP_ENOTPD",
                 -5: "HSP_ERANGE", -6: "HSP_EPOISONED"}
 
-EXPORTS = ["hsp_default_options", "hsp_max_p", "hsp_gram", "hsp_create", "hsp_sweep", "hsp_sync", "hsp_draws",
+EXPORTS = ["hsp_default_options", "hsp_max_p", "hsp_gram", "hsp_gram_noalloc", "hsp_create", "hsp_sweep", "hsp_sync", "hsp_draws",
            "hsp_destroy", "hsp_last_error", "hsp_get_state", "hsp_set_state", "hsp_step",
            "hsp_get_debug", "hsp_get_gram", "hsp_get_counters", "hsp_set_timing",
            "hsp_get_timing", "hsp_philox", "hsp_set_phase_trace", "hsp_get_phase_trace",
@@ -71,6 +71,7 @@ def load():
     L.hsp_create.argtypes = [vp, vp, i64, i64, C.POINTER(hsp_options), C.POINTER(vp)]
     L.hsp_create.restype = st
     L.hsp_gram.argtypes = [vp, i32, i64, i64, i64, vp, vp]; L.hsp_gram.restype = st
+    L.hsp_gram_noalloc.argtypes = [vp, i32, i64, i64, i64, vp, vp]; L.hsp_gram_noalloc.restype = st
     L.hsp_sweep.argtypes = [vp, i64]; L.hsp_sweep.restype = st
     L.hsp_sync.argtypes = [vp]; L.hsp_sync.restype = st
     L.hsp_draws.argtypes = [vp, vp, vp, vp, i64, i64, C.POINTER(i64)]; L.hsp_draws.restype = st
@@ -143,6 +144,11 @@ def hsp_max_p():
 def hsp_gram(X, x_type, N, p, ld, G, stream=None):
     """G = X^T X (float64) of a device design; X and G are device pointers (int)."""
     _check(load().hsp_gram(X, x_type, N, p, ld, G, stream))
+
+
+def hsp_gram_noalloc(X, x_type, N, p, ld, G, stream=None):
+    """hsp_gram through the library's fixed workspace (no device allocation)."""
+    _check(load().hsp_gram_noalloc(X, x_type, N, p, ld, G, stream))
 
 
 def hsp_create(X, y, N, p, opt=None):
