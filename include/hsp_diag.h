@@ -40,13 +40,13 @@ hsp_status hsp_get_phase_trace(hsp_state* s, uint64_t* out, int64_t* group_block
  * Task code: type (bits 0-1: 0 factor a diagonal tile, 1 triangular solve of
  * a tile of the block row, 2 tile update, 3 the next diagonal tile's solve,
  * update and factorisation in one block) | part (bit 2: 0 U, 1 L^-1) | step
- * k (bits 3-9) | tile row i (bits 10-16) | tile column j (bits 17-23).
+ * k (bits 3-10) | tile row i (bits 11-18) | tile column j (bits 19-26).
  * With gp = 1, off[0..1] delimits block 0's list; with gp > 1, off[0..1]
  * delimits block 0's list (the critical chain) and off[1..2] the shared
  * queue that the other blocks claim tasks from, in order.  tasks (capacity
  * cap) receives the lists, off (3 entries) their bounds, *n_tasks the total
  * count (also when cap is too small, then HSP_ERANGE).  Errors: HSP_EINVAL
- * if nt < 1, nt > 64 or gp < 1.  Test hook for the schedule's coverage and
+ * if nt < 1, nt > hsp_max_p() / 64 or gp < 1.  Test hook for the schedule's coverage and
  * deadlock freedom. */
 hsp_status hsp_tile_schedule(int64_t nt, int64_t gp, uint32_t* tasks, int64_t cap, uint32_t* off,
                              int64_t* n_tasks);

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
+#include <array>
 #include <string>
 #include <vector>
 
@@ -1060,7 +1061,8 @@ uint32_t count_tasks(uint32_t nt) {
 // type and one z-pass tile height R (rows per wave tile): the pack's kernel
 // is built for its widest rows, and a wider kernel of the same R sums every
 // tile of a narrower chain exactly as that chain's own kernel does (its extra
-// columns are zeros), so a chain draws in a pack what it draws alone.
+// columns are zeros), so a chain draws in a pack what it draws alone.  Rows
+// split over a block's waves are packed only with rows of the same split.
 hsp_status plan_packs(hsp_batch* b) {
     const int num_cus = b->chains[0]->num_cus;
     std::vector<bool> taken(b->chains.size(), false);
@@ -1101,12 +1103,24 @@ hsp_status plan_packs(hsp_batch* b) {
             }
         }
     }
-    for (int xt = 0; xt < 2; ++xt)
-    for (int R : {8, 4, 2}) {
+    // Packs by (storage type, tile height R, and for rows split over the
+    // waves the exact split): the row sums of a wide row depend on where the
+    // waves' quarters start.
+    auto key_of = [&](size_t i) {
+        const hsp_state* c = b->chains[i];
+        const int xt = c->x.xtype, kc = c->plan.chunks;
+        return std::array<int, 3>{xt, rows_for(xt, kc), wide_chunks(xt, kc) ? kc : 0};
+    };
+    std::vector<std::array<int, 3>> keys;
+    for (size_t i = 0; i < b->chains.size(); ++i)
+        if (!taken[i] && std::find(keys.begin(), keys.end(), key_of(i)) == keys.end()) keys.push_back(key_of(i));
+    std::sort(keys.begin(), keys.end());
+    for (const auto& key : keys) {
+        const int xt = key[0];
         std::vector<size_t> ids;
         int chunks = 1;
         for (size_t i = 0; i < b->chains.size(); ++i)
-            if (!taken[i] && b->chains[i]->x.xtype == xt && rows_for_chunks(b->chains[i]->plan.chunks) == R) {
+            if (!taken[i] && key_of(i) == key) {
                 ids.push_back(i);
                 chunks = std::max(chunks, b->chains[i]->plan.chunks);
             }
@@ -1116,7 +1130,7 @@ hsp_status plan_packs(hsp_batch* b) {
         // bytes per microsecond per block (about 7 TB/s in all, scaled by the tuner)
         const double bw = 7.0e6 / cap * (b->bw_pct / 100.0);
         std::vector<ChainCost> cost(b->chains.size());
-        const int rows = rows_for_chunks(chunks);
+        const int rows = rows_for(xt, chunks);
         for (size_t i : ids) {
             const hsp_state* s = b->chains[i];
             ChainCost& c = cost[i];
@@ -1730,8 +1744,8 @@ hsp_status hsp_set_phase_trace(hsp_state* s, int32_t enable) {
         s->trace = nullptr;
     }
     if (enable) {
-        HIP_TRY(dalloc(&s->trace, (size_t)kMaxGroup * kTraceSlots));
-        HIP_TRY(hipMemsetAsync(s->trace, 0, (size_t)kMaxGroup * kTraceSlots * 8, s->stream));
+        HIP_TRY(dalloc(&s->trace, (size_t)s->plan.capacity * kTraceSlots));
+        HIP_TRY(hipMemsetAsync(s->trace, 0, (size_t)s->plan.capacity * kTraceSlots * 8, s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
     }
     SweepArgs h;

@@ -35,7 +35,8 @@ inline HSP_GLOBAL T* dev_ptr(T* p) {
 }
 
 constexpr int kWave = 64;
-constexpr int kMaxP = 4096;            // largest p the register-tiled z pass supports
+constexpr int kMaxP = 10240;           // largest p
+constexpr uint32_t kLargeP = 4096;     // beyond this p the factorisation outweighs the pass over X
 constexpr uint32_t kMaxRounds = 2048;  // 4096 truncated-normal proposals per row
 constexpr int kThreads = 256;          // threads per block of the sweep kernel
 constexpr int kTile = 64;              // p-side tile edge
@@ -45,9 +46,18 @@ constexpr int kSmallP = 16;            // p up to this runs the one-block p-side
 #endif
 constexpr int kMaxGroup = HSP_MAX_GROUP;  // most blocks of the p-side group
 constexpr int kZGroup = 16;            // z-pass blocks whose partials one block sums
-// Rows per wave tile of the z pass for rows of kc 16-byte chunks per lane
-// (the register budget: taller tiles for kc <= 2 spill).
-constexpr int rows_for_chunks(int kc) { return kc <= 4 ? 8 : (kc <= 8 ? 4 : 2); }
+// The z pass for rows of kc 16-byte chunks per lane of a wave (xtype 0:
+// float32, 4 elements per chunk; 1: bfloat16, 8): whether each wave holds
+// whole rows (up to 1536 float32 or 1024 bfloat16 elements) or the row is
+// split over the block's four waves, and the rows per tile.  Both are set by
+// the register budget of two blocks per compute unit: a taller tile or a
+// whole wider row in one wave spills.
+constexpr bool wide_chunks(int xtype, int kc) { return xtype == 0 ? kc > 6 : kc > 2; }
+constexpr int rows_for(int xtype, int kc) {
+    if (!wide_chunks(xtype, kc)) return kc <= 4 ? 8 : 4;
+    const int kcw = (kc + 3) / 4;  // chunks per lane of each wave's quarter
+    return xtype == 0 ? (kcw <= 3 ? 4 : kcw <= 7 ? 2 : 1) : (kcw <= 2 ? 4 : kcw <= 4 ? 2 : 1);
+}
 // How the z pass deals out its row tiles (a launch parameter; the autotuner
 // may pick others): this share in percent statically, interleaved over all
 // waves, the rest in units of this many tiles to whichever block asks next.
@@ -200,10 +210,11 @@ constexpr int kTraceRecs = 5;
 
 // ---- tasks of the tiled factorisation (p > 16) ----------------------------------
 enum : uint32_t { kTaskPotrf = 0u, kTaskTrsm = 1u, kTaskGemm = 2u, kTaskPanel = 3u };
-// type (2 bits) | part (0: U, 1: L^-1) | step k | tile row i | tile column j (7 bits each)
+// type (2 bits) | part (0: U, 1: L^-1) | step k | tile row i | tile column j (8 bits each)
+constexpr uint32_t kTaskField = 255u;  // nt <= 255 tiles per side
 __host__ __device__ constexpr uint32_t task_code(uint32_t type, uint32_t part, uint32_t k, uint32_t i,
                                                  uint32_t j) {
-    return type | part << 2 | k << 3 | i << 10 | j << 17;
+    return type | part << 2 | k << 3 | i << 11 | j << 19;
 }
 // Task lists of the factorisation of [Q | I] for a group of gp blocks
 // (schedule.cpp): with gp = 1 one list, tasks[off[0] .. off[1]), run in order by

@@ -740,8 +740,8 @@ __device__ bool run_tasks(Args& a, Group& g, uint32_t rank, double tau, Tile& S,
     }
     while (n < n1) {
         const uint32_t code = a.tasks[n];
-        const uint32_t type = code & 3u, part = (code >> 2) & 1u, kb = (code >> 3) & 127u,
-                       ib = (code >> 10) & 127u, jb = (code >> 17) & 127u;
+        const uint32_t type = code & 3u, part = (code >> 2) & 1u, kb = (code >> 3) & kTaskField,
+                       ib = (code >> 11) & kTaskField, jb = (code >> 19) & kTaskField;
         uint32_t reserved = 0;
         if (threadIdx.x == 0) {
             if (queue) reserved = atomicAdd(&a.ctrl->task_next, 1u);
@@ -898,19 +898,19 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
         __syncthreads();
     }
     // b = X^T z into LDS (zero on the padding), as the z groups accumulated
-    // it; block 0 also stores it.
+    // it; block 0 also stores it.  A vector too long for the LDS (big) is
+    // read from memory where it is used instead.
+    const bool big = P + 16 * 17 > (uint32_t)kLdsDoubles;
+    const bool from_sum = (a.mode & (kModeZ | kModeBsum)) != 0;
+    auto b_at = [&](uint32_t j) -> double {
+        if (j >= p) return 0.0;
+        return from_sum ? ldc(&a.bsum[j]) * a.xscale[j] : a.b[j];  // unscaled exactly
+    };
     double* bl = lds;
     for (uint32_t j = threadIdx.x; j < P; j += kThreads) {
-        double s = 0.0;
-        if (j < p) {
-            if (a.mode & (kModeZ | kModeBsum)) {
-                s = ldc(&a.bsum[j]) * a.xscale[j];  // unscaled exactly
-                if (rank == 0) a.b[j] = s;
-            } else {
-                s = a.b[j];
-            }
-        }
-        bl[j] = s;
+        const double s = b_at(j);
+        if (from_sum && rank == 0 && j < p) a.b[j] = s;
+        if (!big) bl[j] = s;
     }
     __syncthreads();
 
@@ -931,7 +931,7 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
                 double x[4][4], bj[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    bj[u] = bl[j + 64 * u];
+                    bj[u] = big ? b_at(j + 64 * u) : bl[j + 64 * u];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) x[u][r] = ldc(L0 + (size_t)r * P + j + 64 * u);
                 }
@@ -941,7 +941,7 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
                     for (int r = 0; r < 4; ++r) acc[r] = fma(x[u][r], bj[u], acc[r]);
             }
             for (; j < jn; j += 64) {
-                const double bj = bl[j];
+                const double bj = big ? b_at(j) : bl[j];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) acc[r] = fma(ldc(L0 + (size_t)r * P + j), bj, acc[r]);
             }
@@ -963,8 +963,10 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
         // every block reads about the same number of rows; 16 row groups per
         // column, four rows of loads in flight each.
         double* yl = lds;
-        for (uint32_t j = threadIdx.x; j < P; j += kThreads) yl[j] = j < p ? ldc(&yv[j]) : 0.0;
-        double* red = lds + P;
+        if (!big)
+            for (uint32_t j = threadIdx.x; j < P; j += kThreads) yl[j] = j < p ? ldc(&yv[j]) : 0.0;
+        auto y_at = [&](uint32_t i) -> double { return big ? (i < p ? ldc(&yv[i]) : 0.0) : yl[i]; };
+        double* red = big ? lds : lds + P;
         __syncthreads();
         bool keep;
         const uint32_t slot = record_slot(a, k, &keep);
@@ -985,12 +987,12 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
 #pragma unroll
                     for (int u = 0; u < 16; ++u) x[u] = ldc(Lc + (size_t)(i + 16 * u) * P);
 #pragma unroll
-                    for (int u = 0; u < 16; ++u) acc[u & 3] = fma(x[u], yl[i + 16 * u], acc[u & 3]);
+                    for (int u = 0; u < 16; ++u) acc[u & 3] = fma(x[u], y_at(i + 16 * u), acc[u & 3]);
                 }
                 for (; i + 48 < P; i += 64)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) acc[u] = fma(ldc(Lc + (size_t)(i + 16 * u) * P), yl[i + 16 * u], acc[u]);
-                for (; i < P; i += 16) acc[0] = fma(ldc(Lc + (size_t)i * P), yl[i], acc[0]);
+                    for (int u = 0; u < 4; ++u) acc[u] = fma(ldc(Lc + (size_t)(i + 16 * u) * P), y_at(i + 16 * u), acc[u]);
+                for (; i < P; i += 16) acc[0] = fma(ldc(Lc + (size_t)i * P), y_at(i), acc[0]);
                 red[tr * 17 + tc] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
                 __syncthreads();
                 if (tr == 0 && col < p) {

@@ -28,20 +28,22 @@ namespace {
 // A launch may serve several independent chains (a batch): block b belongs
 // to chain chain_of_block[b] (chain 0 for all when the map is null) and runs
 // that chain's role at position b - block0 of its blocks.
-template <int XT, int KC, int R>
+template <int XT, int KC, int R, bool WIDE>
 __device__ __forceinline__ void run_block(Args& a, double* lds) {
     const uint32_t b = blockIdx.x - a.block0;
     const uint32_t k = a.ctrl->sweep + 1u;
     if (b < a.gp) pside_role(a, b, k, lds);
-    else zpass_role<XT, KC, R>(a, b - a.gp, a.gz, k, lds);
+    else zpass_role<XT, KC, R, WIDE>(a, b - a.gp, a.gz, k, lds);
 }
 
-template <int XT, int KC, int R>
+// KC: 16-byte chunks per lane of a wave (of the whole row, or with WIDE of
+// the wave's quarter of it); R: rows per tile.
+template <int XT, int KC, int R, bool WIDE>
 __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(const SweepArgs* const* __restrict__ args,
                                                             const uint16_t* __restrict__ chain_of_block) {
     __shared__ double lds[kLdsDoubles];
     const uint32_t c = chain_of_block ? chain_of_block[blockIdx.x] : 0u;
-    run_block<XT, KC, R>(*(Args*)args[c], lds);
+    run_block<XT, KC, R, WIDE>(*(Args*)args[c], lds);
 }
 
 
@@ -60,13 +62,26 @@ using KernelFn = void (*)(const SweepArgs* const*, const uint16_t*);
 template <int XT, int... KCs>
 KernelFn pick(int kc, std::integer_sequence<int, KCs...>) {
     KernelFn f = nullptr;
-    ((kc == KCs + 1 ? (f = &sweep_kernel<XT, KCs + 1, rows_for_chunks(KCs + 1)>, 0) : 0), ...);
+    ((kc == KCs + 1 ? (f = &sweep_kernel<XT, KCs + 1, rows_for(XT, KCs + 1), false>, 0) : 0), ...);
+    return f;
+}
+
+// wide rows: kcw chunks per lane of each wave's quarter
+template <int XT, int... KCs>
+KernelFn pick_wide(int kcw, std::integer_sequence<int, KCs...>) {
+    KernelFn f = nullptr;
+    ((kcw == KCs + 1 ? (f = &sweep_kernel<XT, KCs + 1, rows_for(XT, 4 * (KCs + 1)), true>, 0) : 0), ...);
     return f;
 }
 
 KernelFn kernel_for(int xtype, int chunks) {
-    if (xtype == 0) return pick<0>(chunks, std::make_integer_sequence<int, kMaxP / (kWave * 4)>{});
-    return pick<1>(chunks, std::make_integer_sequence<int, kMaxP / (kWave * 8)>{});
+    if (!wide_chunks(xtype, chunks)) {
+        if (xtype == 0) return pick<0>(chunks, std::make_integer_sequence<int, 6>{});
+        return pick<1>(chunks, std::make_integer_sequence<int, 2>{});
+    }
+    const int kcw = (chunks + 3) / 4;
+    if (xtype == 0) return pick_wide<0>(kcw, std::make_integer_sequence<int, kMaxP / (kWave * 4 * 4)>{});
+    return pick_wide<1>(kcw, std::make_integer_sequence<int, kMaxP / (kWave * 8 * 4)>{});
 }
 
 }  // namespace
@@ -74,15 +89,23 @@ KernelFn kernel_for(int xtype, int chunks) {
 uint32_t max_group(const XLayout& x, int capacity) {
     const uint32_t nt = (x.p + kTile - 1) / kTile;
     uint32_t gp = x.p <= (uint32_t)kSmallP ? 1u : nt * (nt + 1) / 2;
-    if (gp > (uint32_t)kMaxGroup) gp = kMaxGroup;
-    if (gp > (uint32_t)capacity / 4) gp = capacity / 4 > 0 ? capacity / 4 : 1;
+    if (x.p <= kLargeP) {
+        // the factorisation hides under the z pass: a quarter of the device at most
+        if (gp > (uint32_t)kMaxGroup) gp = kMaxGroup;
+        if (gp > (uint32_t)capacity / 4) gp = capacity / 4 > 0 ? capacity / 4 : 1;
+    } else {
+        // p^3 / 3 flops per sweep outweigh the pass over X: three quarters
+        const uint32_t cap = (uint32_t)capacity * 3 / 4;
+        if (gp > cap) gp = cap > 0 ? cap : 1;
+    }
     return gp;
 }
 
 hipError_t sweep_plan(const XLayout& x, int num_cus, SweepPlan* plan, uint32_t gp_req) {
     const int vec = x.xtype == 0 ? 4 : 8;
     plan->chunks = (int)((x.ld + kWave * vec - 1) / (kWave * vec));
-    plan->rows = rows_for_chunks(plan->chunks);
+    plan->rows = rows_for(x.xtype, plan->chunks);
+    const bool wide = wide_chunks(x.xtype, plan->chunks);
     KernelFn f = kernel_for(x.xtype, plan->chunks);
     if (!f) return hipErrorInvalidValue;
     int per_cu = 0;
@@ -95,7 +118,8 @@ hipError_t sweep_plan(const XLayout& x, int num_cus, SweepPlan* plan, uint32_t g
     if (gp_req > 0 && gp_req < gp) gp = gp_req;
     plan->gp = gp;
     const uint64_t tiles = (x.N + plan->rows - 1) / plan->rows;
-    uint64_t gz = (tiles + kWPB - 1) / kWPB;
+    // a wave takes a tile (a block, for wide rows)
+    uint64_t gz = wide ? tiles : (tiles + kWPB - 1) / kWPB;
     const uint64_t room = (uint64_t)plan->capacity - gp;
     if (gz > room) gz = room;
     if (gz < 1) gz = 1;

@@ -90,7 +90,13 @@ __device__ __forceinline__ void tn_candidate(float mu, bool gauss, float theta, 
 }
 
 // The z-pass role of the sweep kernel: block zrank of nz z-pass blocks.
-template <int XT, int KC, int R>
+// Short rows (WIDE false, see wide_chunks): each wave holds whole rows,
+// KC chunks per lane, and takes tiles on its own.  Wider rows (WIDE): the
+// block's four waves split every row into quarters of KC chunks per lane
+// and take each tile together; their partial dot products meet in LDS and
+// are added in wave order, so every wave holds the same eta and draws the
+// same z, and each wave sums x_i^T z_i over its own quarter of the columns.
+template <int XT, int KC, int R, bool WIDE = false>
 __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
                                            uint32_t ksweep, double* red) {
     if (zrank >= nz) return;  // no z-pass work in this launch
@@ -104,6 +110,7 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
     const uint32_t N = a.x.N;
     const char* __restrict__ Xb = static_cast<const char*>(a.x.X);
     const size_t row_bytes = (size_t)ld * EB;
+    const uint32_t c0 = WIDE ? (uint32_t)wave * KC * CW : 0u;  // first column of this wave's part
 
     float bl[KC][VEC];
     double bacc[KC][VEC];
@@ -111,15 +118,18 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
     for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            const uint32_t col = kc * CW + lane * VEC + e;
+            const uint32_t col = c0 + kc * CW + lane * VEC + e;
             bl[kc][e] = col < ld ? a.beta32[col] : 0.0f;
             bacc[kc][e] = 0.0;
         }
 
     const uint32_t n_tiles = (N + R - 1) / R;
-    const uint32_t W = nz * kWPB;
+    // tiles are taken by waves, or for wide rows by whole blocks
+    const uint32_t W = WIDE ? nz : nz * kWPB;
     uint32_t maxatt = 0;
     bool capped = false;
+    uint32_t parity = 0;                // wide rows: LDS slot of the next tile's partial sums
+    double* eta_lds = red + 8;          // [2][kWPB][R], after the unit slot
 
     auto tile = [&](uint32_t t) {
         const uint32_t row0 = t * R;
@@ -129,7 +139,7 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
                 const uint32_t row = row0 + r;
-                const uint32_t col = kc * CW + lane * VEC;
+                const uint32_t col = c0 + kc * CW + lane * VEC;
                 if (row < N && col < ld) {
 #if HSP_X_NONTEMPORAL
                     const U32x4 v = __builtin_nontemporal_load(
@@ -157,6 +167,24 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
         for (int off = kWave / 2; off >= 1; off >>= 1)
 #pragma unroll
             for (int r = 0; r < R; ++r) s[r] += __shfl_xor(s[r], off);
+        if constexpr (WIDE) {
+            // the four quarters' sums through LDS, added in wave order; the
+            // two slots alternate, so one barrier per tile keeps a slot from
+            // being rewritten before every wave has read it
+            double* slotp = eta_lds + parity * (kWPB * R);
+            if (lane == 0)
+#pragma unroll
+                for (int r = 0; r < R; ++r) slotp[wave * R + r] = (double)s[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float v = (float)slotp[r];
+#pragma unroll
+                for (int w = 1; w < kWPB; ++w) v += (float)slotp[w * R + r];
+                s[r] = v;
+            }
+            parity ^= 1u;
+        }
         float eta = s[0];
 #pragma unroll
         for (int r = 1; r < R; ++r) eta = (lane == r) ? s[r] : eta;
@@ -197,7 +225,7 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
                 }
             }
         }
-        if (active) {
+        if (active && (!WIDE || wave == 0)) {
             maxatt = max(maxatt, (uint32_t)(att + 1));
             if (a.zdbg) {
                 a.zdbg[grow] = zval;
@@ -227,7 +255,7 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
     // next unit before working on the current one.
     const uint32_t unit = a.z_unit;
     const uint32_t n_static = (uint32_t)((uint64_t)n_tiles * a.z_static_pct / 100 / W * W);
-    for (uint32_t t = zrank * kWPB + wave; t < n_static; t += W) tile(t);
+    for (uint32_t t = WIDE ? zrank : zrank * kWPB + wave; t < n_static; t += W) tile(t);
     if (n_static < n_tiles) {
         const uint32_t n_units = (n_tiles - n_static + unit - 1) / unit;
         double* slot = red;  // free until the reduction below
@@ -238,7 +266,7 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
         while (u < n_units) {
             uint32_t next = 0;
             if (threadIdx.x == 0) next = atomicAdd(&a.ctrl->z_next, 1u);
-            for (uint32_t j = wave; j < unit; j += kWPB) {
+            for (uint32_t j = WIDE ? 0u : (uint32_t)wave; j < unit; j += WIDE ? 1u : (uint32_t)kWPB) {
                 const uint32_t t = n_static + u * unit + j;
                 if (t < n_tiles) tile(t);
             }
@@ -259,8 +287,18 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
         if (anycap) atomicOr(&a.ctrl->err, kErrTnCap);
     }
 
-    // block partial of X^T z: the waves' float64 sums added in wave order
-    for (uint32_t seg = 0; seg < ld; seg += kRedCols) {
+    // block partial of X^T z: for wide rows, every wave's own columns; else
+    // the waves' float64 sums added in wave order
+    if constexpr (WIDE) {
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const uint32_t col = c0 + kc * CW + lane * VEC + e;
+                if (col < ld) stc(&a.partial[(size_t)zrank * ld + col], bacc[kc][e]);
+            }
+    }
+    for (uint32_t seg = 0; !WIDE && seg < ld; seg += kRedCols) {
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc)
 #pragma unroll

@@ -20,7 +20,7 @@ POTRF, TRSM, GEMM, PANEL = 0, 1, 2, 3
 
 
 def decode(c):
-    return c & 3, (c >> 2) & 1, (c >> 3) & 127, (c >> 10) & 127, (c >> 17) & 127
+    return c & 3, (c >> 2) & 1, (c >> 3) & 255, (c >> 11) & 255, (c >> 19) & 255
 
 
 def expected_tasks(nt, chain):
@@ -136,7 +136,7 @@ def lists_of(nt, gp):
     return dec[off[0]:off[1]], dec[off[1]:off[2]], gp - 1
 
 
-@pytest.mark.parametrize("nt,gp", [(1, 1), (2, 1), (3, 2), (5, 32), (16, 32), (16, 7), (20, 32)])
+@pytest.mark.parametrize("nt,gp", [(1, 1), (2, 1), (3, 2), (5, 32), (16, 32), (16, 7), (20, 32), (40, 96)])
 def test_schedule_covers_every_task_and_never_deadlocks(nt, gp):
     tasks, off = hsp.hsp_tile_schedule(nt, gp)
     assert off[0] == 0 and off[-1] == len(tasks) and np.all(np.diff(off.astype(np.int64)) >= 0)
@@ -161,10 +161,21 @@ def test_schedule_shortens_with_more_blocks():
     assert spans[32] < spans[4] < spans[2]
 
 
+def test_schedule_beyond_127_tiles():
+    """p = 10,000 (157 tiles per side, a group of 384 blocks): every task once,
+    its fields decoded intact, and the critical chain in order."""
+    nt, gp = 157, 384
+    tasks, off = hsp.hsp_tile_schedule(nt, gp)
+    chain_list, queue, _ = lists_of(nt, gp)
+    dec = chain_list + queue
+    assert len(dec) == len(set(dec)) and set(dec) == expected_tasks(nt, True)
+    assert chain_list == [(POTRF, 0, 0, 0, 0)] + [(PANEL, 0, k, k, k) for k in range(1, nt)]
+
+
 def test_schedule_rejects_bad_arguments():
     with pytest.raises(hsp.HspError):
         hsp.hsp_tile_schedule(0, 4)
     with pytest.raises(hsp.HspError):
-        hsp.hsp_tile_schedule(65, 4)
+        hsp.hsp_tile_schedule(hsp.hsp_max_p() // 64 + 1, 4)
     with pytest.raises(hsp.HspError):
         hsp.hsp_tile_schedule(4, 0)
