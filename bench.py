@@ -26,6 +26,9 @@ line also carries
                 the paper ran, with the lag-1 autocorrelation and effective
                 sample size of the coefficients and the truncated-normal
                 branch mix
+  large_p       N = 1e6, p = 1e4 (40 GB float32 X, generated on the GPU):
+                sweeps/s and the fraction of the FP64 matrix-core peak its
+                factorisation and passes reach
   streamed      the same float32 workload with X in pinned host memory,
                 streamed through the GPU every sweep: its rate against the
                 measured host-to-device link
@@ -56,7 +59,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--N", type=int, default=1_000_000)
     ap.add_argument("--p", type=int, default=1000)
-    ap.add_argument("--only", choices=["f32", "bf16", "batch", "rare", "streamed"], default=None,
+    ap.add_argument("--only", choices=["f32", "bf16", "batch", "rare", "streamed", "large_p"], default=None,
                     help="run one form only and print its own line (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="built-in launch shapes (no autotuner)")
@@ -253,6 +256,68 @@ def run_streamed(a, d, sweeps=20):
     }
 
 
+def run_large_p(a, N=1_000_000, p=10_000, sweeps=20):
+    """The point the paper could not run (Sections 6.1 and 7: N = 1e6,
+    p = 1e4, a 40 GB float32 X): data generated on the GPU (X iid N(0,1) with
+    an intercept column, 10 nonzero coefficients ~ U(-3, 3), probit y), the
+    sweep timed as for the main workload.  Its floor is the float64
+    factorisation (p^3 / 3 flops) as much as the pass over X."""
+    import numpy as np
+    import torch
+
+    from paper_1608_04329_amd import hsp
+    t0 = time.perf_counter()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(14)
+    X = torch.randn((N, p), generator=g, device="cuda", dtype=torch.float32)
+    X[:, 0] = 1.0
+    gc = torch.Generator()
+    gc.manual_seed(14)
+    idx = torch.randperm(p, generator=gc)[:10]
+    beta_true = torch.zeros(p, dtype=torch.float32)
+    beta_true[idx] = (torch.rand(10, generator=gc) * 6.0 - 3.0)
+    eps = torch.randn(N, generator=g, device="cuda", dtype=torch.float32)
+    y = ((X @ beta_true.cuda()) + eps > 0).to(torch.uint8)
+    del eps
+    torch.cuda.synchronize()
+    print(f"[bench] large p: data N={N} p={p} generated on the GPU in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    s = hsp.Sampler(X, y, seed=1, max_draws=64, autotune=not a.no_tune)
+    del X, y
+    torch.cuda.empty_cache()
+    plan = s.plan()
+    print(f"[bench] large p: sampler created (copy, Gram, schedule, plan {plan[4]}) in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    s.sweep(3)
+    s.sync()
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.sweep(sweeps)
+    s.sync()
+    elapsed = time.perf_counter() - t0
+    kernel_ms, _, _ = s.timing()
+    s.set_timing(False)
+    betas, taus, _ = s.draws()
+    s.close()
+    nbytes = N * p * 4 + N
+    flops = p ** 3 / 3.0 + 2.0 * p * p + 4.0 * N * p
+    hbm = roofline(nbytes, kernel_ms, None)
+    fp64 = {"bound": "mfma", "achieved": round(flops / (kernel_ms * 1e-3) / 1e12, 2), "peak": 78.6,
+            "unit": "TFLOP/s", "frac": round(flops / (kernel_ms * 1e-3) / 1e12 / 78.6, 4), "traffic": None,
+            "flops_per_launch": flops, "flops_counted": "p^3/3 Cholesky + 2p^2 solves + 4Np for X beta and X^T z"}
+    return {
+        "workload": f"horseshoe_probit_gibbs_N{N}_p{p}_xf32",
+        "value": round(sweeps / elapsed, 3), "unit": "sweeps/s", "sweeps": sweeps,
+        "ms_per_step": round(1e3 * elapsed / sweeps, 4), "kernel_ms": round(kernel_ms, 4),
+        "launch_plan": {"group_blocks": plan[0], "z_blocks": plan[1], "chosen": plan[4]},
+        "finite_draws": bool(np.isfinite(betas).all() and np.all(taus > 0)),
+        "roofline": fp64 if fp64["frac"] >= hbm["frac"] else hbm,
+        "roofline_hbm": hbm, "roofline_fp64": fp64,
+    }
+
+
 def ess_and_acf(x):
     """Lag-1 autocorrelation and effective sample size of each column of x
     (draws x coefficients): ESS = n / (1 + 2 sum_k rho_k), the sum cut by
@@ -298,6 +363,15 @@ def run_rare(a, sweeps=10_000, burn=2_500):
     s.set_timing(False)
     betas, taus, _ = s.draws()
     _, att, _ = s.debug()
+    # Section 5's variant: rows reordered by y* x_i beta after burn-in, then
+    # the same sweep timed again
+    s.sort_rows()
+    s.sweep(20)
+    s.sync()
+    s.set_timing(True)
+    s.sweep(2000)
+    s.sync()
+    kernel_ms_sorted, _, _ = s.timing()
     s.close()
     gauss = (att & (1 << 30)) != 0
     rho1, ess = ess_and_acf(betas[burn:])
@@ -313,6 +387,7 @@ def run_rare(a, sweeps=10_000, burn=2_500):
         "ess": {"min": round(float(ess.min()), 1), "median": round(float(np.median(ess)), 1),
                 "intercept": round(float(ess[0]), 1)},
         "tn_gauss_branch_fraction": round(float(gauss.mean()), 5),
+        "kernel_ms_rows_sorted": round(kernel_ms_sorted, 5),
         "intercept_posterior_mean": round(float(betas[burn:, 0].mean()), 4),
         "intercept_true": round(float(d.beta_true[0]), 4),
     }
@@ -419,6 +494,14 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
+    if a.only == "large_p":
+        r = run_large_p(a)
+        out = dict(common, value=r["value"], unit=r["unit"], ms_per_step=r["ms_per_step"], dtype="f32+f64",
+                   config={"workload": r["workload"]}, roofline=r["roofline"], large_p=r)
+        out["steps"], out["warmup"] = r["sweeps"], 3
+        print(json.dumps(out), flush=True)
+        return
+
     if a.only == "rare":
         r = run_rare(a)
         out = dict(common, value=r["value"], unit=r["unit"], ms_per_step=round(1e3 / r["value"], 5),
@@ -465,6 +548,10 @@ def main():
             del data
             out["rare_event"] = run_rare(a)
             out["streamed"] = run_streamed(a, d)
+            try:
+                out["large_p"] = run_large_p(a)
+            except Exception as e:  # reported, never fatal to the main line
+                out["large_p"] = {"error": f"{type(e).__name__}: {e}"}
     if not a.no_cpu_baseline and a.only is None:
         print("[bench] timing the float64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(d, a.cpu_seconds)

@@ -200,6 +200,19 @@ hsp_status hsp_sync(hsp_state* s);
 hsp_status hsp_draws(hsp_state* s, double* beta, double* tau_m2, double* lam_m2,
                      int64_t first, int64_t count, int64_t* n_out);
 
+/*
+ * Reorder the library's copy of the rows of X (and y) by y*_i x_i beta of
+ * the current state, y* = 2y - 1 (Section 5 suggests it after burn-in, so
+ * that rows whose truncated normals take the same branch and accept after
+ * similar numbers of proposals share a wave).  Every row keeps its Philox
+ * counters and its place in hsp_get_debug's outputs, so z is drawn exactly
+ * as before; X^T z is then summed over other groups of rows, so b and the
+ * chain change within float32 rounding.  Allocates a second copy of X while
+ * it runs.  Synchronises.  Errors: HSP_EINVAL for a streamed state or a
+ * chain of a batch; HSP_ENOMEM; HSP_EHIP; HSP_EPOISONED.
+ */
+hsp_status hsp_sort_rows(hsp_state* s);
+
 /* Release every resource of the state (waits for its work first).  A chain
  * of a batch is released with its batch (HSP_EINVAL here). */
 hsp_status hsp_destroy(hsp_state* s);

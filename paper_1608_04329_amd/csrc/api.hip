@@ -137,6 +137,7 @@ struct hsp_state {
     const SweepArgs** sdtab = nullptr;
     std::vector<SweepArgs> sd_host;     // host copies of the same
     uint32_t sd_mode = 0;               // the mode they were built for (0: none yet)
+    uint32_t* row_id = nullptr;         // original index of each stored row once reordered (device)
 };
 
 namespace {
@@ -194,6 +195,7 @@ SweepArgs sweep_args(hsp_state* s, uint32_t mode) {
     a.tasks = dev_ptr(s->tasks);
     a.task_off = dev_ptr(s->task_off);
     a.ver = dev_ptr(s->ver);
+    a.row_id = dev_ptr(static_cast<const uint32_t*>(s->row_id));
     a.vec = dev_ptr(s->vec);
     a.ring_beta = dev_ptr(s->ring_beta);
     a.ring_tau = dev_ptr(s->ring_tau);
@@ -281,7 +283,7 @@ void free_state(hsp_state* s) {
     void* bufs[] = {s->Xbuf, s->xexp, s->xscale, s->y, s->ctrl, s->beta, s->lam, s->nu, s->tau, s->xi, s->b, s->G, s->Gp,
                     s->A, s->Linv, s->vec, s->partial, s->beta32, s->zdbg, s->adbg,
                     s->ring_beta, s->ring_tau, s->ring_lam, s->trace, s->bsum,
-                    s->zgrp_count, s->dargs, s->dtab, s->tasks, s->task_off, s->ver};
+                    s->zgrp_count, s->dargs, s->dtab, s->tasks, s->task_off, s->ver, s->row_id};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (s->streamed) {
@@ -466,20 +468,27 @@ hsp_status tune_impl(hsp_state* s) {
     hsp_status st = save_chain(s, &saved);
     if (st) return st;
     const uint32_t gmax = max_group(s->x, s->plan.capacity);
+    // beyond p = 4096 the factorisation sets the pace: only the group size is
+    // tried (each size builds a task schedule of ~p^3 / 10^5 tasks)
+    const bool large = s->x.p > kLargeP;
     std::vector<uint32_t> gps{gmax};
     if (s->x.p > (uint32_t)kSmallP)
-        for (uint32_t pct : {75u, 50u, 33u}) {
+        for (uint32_t pct : large ? std::vector<uint32_t>{67u} : std::vector<uint32_t>{75u, 50u, 33u}) {
             const uint32_t g = std::max<uint32_t>(1, (gmax * pct + 50) / 100);
             if (std::find(gps.begin(), gps.end(), g) == gps.end()) gps.push_back(g);
         }
+    const std::vector<uint32_t> pcts = large ? std::vector<uint32_t>{kZStaticPctDefault}
+                                             : std::vector<uint32_t>{0u, 40u, 75u};
+    const std::vector<uint32_t> units = large ? std::vector<uint32_t>{kZUnitDefault}
+                                              : std::vector<uint32_t>{4u, 8u, 16u};
     // shorter runs for big designs: every candidate sweeps all of X
     const double bytes = (double)s->x.N * s->x.ld * (s->x.xtype == 0 ? 4 : 2);
-    const int timed = bytes > 1e9 ? 4 : 8;
+    const int timed = bytes > 1e10 ? 3 : bytes > 1e9 ? 4 : 8;
     SweepPlan best = s->plan;
     double best_ms = 1e300;
     for (uint32_t gp : gps)
-        for (uint32_t pct : {0u, 40u, 75u})
-            for (uint32_t unit : {4u, 8u, 16u}) {
+        for (uint32_t pct : pcts)
+            for (uint32_t unit : units) {
                 SweepPlan c;
                 HIP_TRY(sweep_plan(s->x, s->num_cus, &c, gp));
                 c.static_pct = pct;
@@ -1826,6 +1835,60 @@ hsp_status hsp_gram_noalloc(const void* X, int32_t x_type, int64_t N, int64_t p,
     const hipStream_t st = static_cast<hipStream_t>(hip_stream);
     HIP_TRY(gram_launch_chunked(x, nullptr, G, work, kGramScratchDoubles, num_cus, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return HSP_OK;
+}
+
+hsp_status hsp_sort_rows(hsp_state* s) {
+    if (!s) return HSP_EINVAL;
+    if (s->poisoned) return HSP_EPOISONED;
+    if (s->streamed || s->in_batch)
+        return fail(s, HSP_EINVAL, "rows can be reordered only for a lone chain with X in device memory");
+    const uint32_t N = s->x.N;
+    const size_t bytes = (size_t)N * s->x.ld * (s->x.xtype == 0 ? 4 : 2);
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    // the key of every stored row, ordered on the host (ties keep their order)
+    float* key = nullptr;
+    HIP_TRY(dalloc(&key, N));
+    std::vector<float> kh(N);
+    hipError_t e = row_key_launch(s->x, s->beta32, s->y, key, s->stream);
+    if (!e) e = hipMemcpyAsync(kh.data(), key, (size_t)N * 4, hipMemcpyDeviceToHost, s->stream);
+    if (!e) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(key);
+    HIP_TRY(e);
+    std::vector<uint32_t> perm(N);
+    for (uint32_t i = 0; i < N; ++i) perm[i] = i;
+    std::stable_sort(perm.begin(), perm.end(), [&](uint32_t a, uint32_t b) { return kh[a] < kh[b]; });
+    uint32_t* dperm = nullptr;
+    void* Xo = nullptr;
+    uint8_t* yo = nullptr;
+    uint32_t* ido = nullptr;
+    e = dalloc(&dperm, N);
+    if (!e) e = hipMalloc(&Xo, bytes);
+    if (!e) e = dalloc(&yo, N);
+    if (!e) e = dalloc(&ido, N);
+    if (!e) e = hipMemcpyAsync(dperm, perm.data(), (size_t)N * 4, hipMemcpyHostToDevice, s->stream);
+    if (!e) e = gather_rows_launch(s->x, dperm, Xo, s->y, yo, s->row_id, ido, s->stream);
+    if (!e) e = hipStreamSynchronize(s->stream);
+    if (dperm) (void)hipFree(dperm);
+    if (e) {
+        if (Xo) (void)hipFree(Xo);
+        if (yo) (void)hipFree(yo);
+        if (ido) (void)hipFree(ido);
+        HIP_TRY(e);
+    }
+    (void)hipFree(s->Xbuf);
+    (void)hipFree(s->y);
+    if (s->row_id) (void)hipFree(s->row_id);
+    s->Xbuf = Xo;
+    s->x.X = dev_ptr(static_cast<const void*>(Xo));
+    s->y = yo;
+    s->row_id = ido;
+    SweepArgs h;
+    HIP_TRY(put_args(s, kModeSweep, 0, &h));
+    if (s->graph) {
+        (void)hipGraphExecDestroy(s->graph);
+        s->graph = nullptr;
+    }
     return HSP_OK;
 }
 

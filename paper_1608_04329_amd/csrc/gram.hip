@@ -296,6 +296,38 @@ hipError_t pad_gram_launch(const double* G, uint32_t p, uint32_t P, double* Gp, 
     return hipGetLastError();
 }
 
+// key[i] = (2 y_i - 1) sum_j x_ij beta32_j: one wave per row (lanes over
+// columns, a wave-wide sum), float32, over the stored column-scaled X.
+__global__ __launch_bounds__(256) void row_key_kernel(XLayout x, const float* __restrict__ b32,
+                                                      const uint8_t* __restrict__ y, float* __restrict__ key) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t waves = gridDim.x * (blockDim.x / 64u);
+    for (uint32_t i = blockIdx.x * (blockDim.x / 64u) + threadIdx.x / 64u; i < x.N; i += waves) {
+        float acc = 0.0f;
+        for (uint32_t j = lane; j < x.p; j += 64u) acc = fmaf(load_x(x, i, j), b32[j], acc);
+        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) key[i] = y[i] ? acc : -acc;
+    }
+}
+
+// Row i of Xo is row perm[i] of X (16-byte vectors; a row is ld elements,
+// a multiple of 16 bytes), with y and the original row indices alongside.
+__global__ __launch_bounds__(256) void gather_rows_kernel(XLayout x, const uint32_t* __restrict__ perm,
+                                                          uint4* __restrict__ Xo, const uint8_t* __restrict__ y,
+                                                          uint8_t* __restrict__ yo, const uint32_t* __restrict__ id,
+                                                          uint32_t* __restrict__ ido) {
+    const size_t vpr = (size_t)x.ld * (x.xtype == 0 ? 4 : 2) / 16;  // 16-byte vectors per row
+    const uint4* X = static_cast<const uint4*>(x.X);
+    for (uint32_t i = blockIdx.x; i < x.N; i += gridDim.x) {
+        const uint32_t src = perm[i];
+        for (size_t v = threadIdx.x; v < vpr; v += blockDim.x) Xo[(size_t)i * vpr + v] = X[(size_t)src * vpr + v];
+        if (threadIdx.x == 0) {
+            yo[i] = y[src];
+            ido[i] = id ? id[src] : src;
+        }
+    }
+}
+
 // Read ceiling: stream `bytes` (a multiple of 16) with eight 16-byte
 // non-temporal loads in flight per lane, grid-stride, the same kind of load
 // as the z pass, and nothing else.
@@ -325,6 +357,18 @@ hipError_t stream_read_launch(const void* x, size_t bytes, int num_cus, float* s
     const unsigned blocks = (unsigned)(2 * num_cus);
     hipLaunchKernelGGL(stream_read_kernel, dim3(blocks), dim3(256), 0, st,
                        static_cast<const RdVec*>(x), n16, sink);
+    return hipGetLastError();
+}
+
+hipError_t row_key_launch(const XLayout& x, const float* beta32, const uint8_t* y, float* key, hipStream_t st) {
+    hipLaunchKernelGGL(row_key_kernel, dim3(4096), dim3(256), 0, st, x, beta32, y, key);
+    return hipGetLastError();
+}
+
+hipError_t gather_rows_launch(const XLayout& x, const uint32_t* perm, void* Xo, const uint8_t* y, uint8_t* yo,
+                              const uint32_t* id, uint32_t* ido, hipStream_t st) {
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(8192), dim3(256), 0, st, x, perm, static_cast<uint4*>(Xo), y, yo,
+                       id, ido);
     return hipGetLastError();
 }
 

@@ -168,6 +168,7 @@ struct SweepArgs {
     uint32_t z_unit;         // z pass: tiles per claimed unit of the rest (1..kZUnitMax)
     uint32_t first_row;      // global index of x.X's first row (X streamed in row chunks; else 0):
                              // y, the Philox counters and the debug outputs use global rows
+    HSP_GLOBAL const uint32_t* row_id;  // original index of each stored row (rows reordered), or null
 };
 
 // Device view of a launch description.
@@ -312,6 +313,13 @@ hipError_t colmax_launch(const float* src, uint32_t N, uint32_t p, uint32_t* col
 // library layout, column j multiplied by 2^-e[j] (exact).  src may be the
 // destination itself when the layouts coincide (float32, ld = p).
 hipError_t pack_x_launch(const float* src, const XLayout& dst, const int32_t* e, hipStream_t st);
+
+// Reordering the stored rows: key[i] = (2 y_i - 1) x_i beta (float32, the
+// stored, column-scaled X with beta32), then Xo[i] = X[perm[i]], yo[i] =
+// y[perm[i]], ido[i] = id ? id[perm[i]] : perm[i] (Xo, X: same layout).
+hipError_t row_key_launch(const XLayout& x, const float* beta32, const uint8_t* y, float* key, hipStream_t st);
+hipError_t gather_rows_launch(const XLayout& x, const uint32_t* perm, void* Xo, const uint8_t* y, uint8_t* yo,
+                              const uint32_t* id, uint32_t* ido, hipStream_t st);
 
 // Stream `bytes` of x with plain 16-byte loads only (the read ceiling).
 hipError_t stream_read_launch(const void* x, size_t bytes, int num_cus, float* sink, hipStream_t st);

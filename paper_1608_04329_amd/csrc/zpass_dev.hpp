@@ -189,12 +189,15 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
 #pragma unroll
         for (int r = 1; r < R; ++r) eta = (lane == r) ? s[r] : eta;
 
-        // lane r < R draws z for row row0 + r (global row first_row + row0 + r
-        // when X arrives in row chunks)
+        // lane r < R draws z for row row0 + r: position first_row + row0 + r of
+        // the stored X and y (X may arrive in row chunks), whose original row
+        // index (the rows may have been reordered) sets its Philox counters
+        // and its place in the debug outputs
         const uint32_t row = row0 + (uint32_t)lane;
         const bool active = lane < R && row < N;
-        const uint32_t grow = a.first_row + row;
-        const float ys = (active && a.y[grow]) ? 1.0f : -1.0f;
+        const uint32_t pos = a.first_row + row;
+        const uint32_t grow = active ? (a.row_id ? a.row_id[pos] : pos) : 0u;
+        const float ys = (active && a.y[pos]) ? 1.0f : -1.0f;
         const float mu = ys * eta;
         const bool gauss = mu > 0.47f;
         const float den = sqrtf(fmaf(mu, mu, 4.0f)) - mu;  // 2 theta

@@ -30,7 +30,7 @@ EXPORTS = ["hsp_default_options", "hsp_max_p", "hsp_gram", "hsp_gram_noalloc", "
            "hsp_tile_schedule", "hsp_read_ceiling", "hsp_batch_create", "hsp_batch_size",
            "hsp_batch_chain", "hsp_batch_sweep", "hsp_batch_sync", "hsp_batch_set_timing",
            "hsp_batch_get_timing", "hsp_batch_last_error", "hsp_batch_destroy", "hsp_get_plan",
-           "hsp_batch_get_plan", "hsp_tune_key", "hsp_tune_cache_put", "hsp_tune_cache_get"]
+           "hsp_sort_rows", "hsp_batch_get_plan", "hsp_tune_key", "hsp_tune_cache_put", "hsp_tune_cache_get"]
 
 
 class hsp_options(C.Structure):
@@ -110,6 +110,7 @@ def load():
     L.hsp_batch_destroy.argtypes = [vp]; L.hsp_batch_destroy.restype = st
     pi64 = C.POINTER(i64)
     L.hsp_get_plan.argtypes = [vp, pi64, pi64, pi64, pi64, C.c_char_p, i64]; L.hsp_get_plan.restype = st
+    L.hsp_sort_rows.argtypes = [vp]; L.hsp_sort_rows.restype = st
     L.hsp_batch_get_plan.argtypes = [vp, pi64, pi64, pi64, C.c_char_p, i64]
     L.hsp_batch_get_plan.restype = st
     L.hsp_tune_key.argtypes = [vp, C.c_char_p, i64]; L.hsp_tune_key.restype = st
@@ -327,6 +328,10 @@ def hsp_get_plan(h):
     return tuple(x.value for x in v) + (note.value.decode(),)
 
 
+def hsp_sort_rows(h):
+    _check(load().hsp_sort_rows(h), h)
+
+
 def hsp_batch_get_plan(b):
     """(mc_blocks, bw_pct, packs, note) of a batch's pack shapes."""
     v = [C.c_int64() for _ in range(3)]
@@ -458,6 +463,9 @@ class Sampler:
 
     def plan(self):
         return hsp_get_plan(self.h)
+
+    def sort_rows(self):
+        hsp_sort_rows(self.h)
 
 
 class Batch:
