@@ -107,8 +107,9 @@ void hsp_default_options(hsp_options* opt);
  * hsp_batch_sweep) picks how the sweep kernel splits its work -- the blocks
  * of the p-side group, and how the z pass deals out its row tiles (a share
  * statically, the rest in claimed units); for a batch, the blocks of each
- * multi-chain z pass and the balance of z-pass and p-side blocks in its
- * packs -- by timing a few sweeps of each candidate on the device.  The
+ * multi-chain z pass, how many chains share a launch, and the balance of
+ * z-pass and p-side blocks in those launches -- by timing a few sweeps of
+ * each candidate on the device.  The
  * chain's state is restored afterwards, and no choice changes any draw:
  * a tuned chain draws bit for bit what an untuned one draws.  If the
  * environment variable HSP_TUNE_CACHE names a file, a choice found there for

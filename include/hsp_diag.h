@@ -75,7 +75,8 @@ hsp_status hsp_get_plan(hsp_state* s, int64_t* group_blocks, int64_t* z_blocks, 
 /* The launch shapes of a batch's packs: blocks of each multi-chain z pass
  * (0: the built-in two per compute unit), the z-pass bandwidth per block that
  * the pack split model assumes (percent of nominal), the number of packs
- * (0 until the first hsp_batch_sweep), and how they were chosen. */
+ * (0 until the first hsp_batch_sweep), and how they were chosen (the note
+ * also gives the most chains per pack the autotuner allowed). */
 hsp_status hsp_batch_get_plan(hsp_batch* b, int64_t* mc_blocks, int64_t* bw_pct, int64_t* packs, char* note,
                               int64_t note_cap);
 

@@ -995,6 +995,7 @@ struct hsp_batch {
     // launch-shape parameters of the packs (the autotuner may change them)
     uint32_t mc_gz = 0;        // blocks of each multi-chain z pass (0: two per compute unit)
     uint32_t bw_pct = 100;     // pack split model: z-pass bandwidth per block, percent of nominal
+    uint32_t pack_max = 0;     // most chains per pack (0: as many as the resident blocks allow)
     bool autotune = false;
     std::string plan_note = "built-in";
 };
@@ -1154,7 +1155,9 @@ hsp_status plan_packs(hsp_batch* b) {
         // packs of at most cap blocks, two blocks per chain at least
         std::vector<std::vector<size_t>> groups;
         for (size_t i : ids) {
-            if (groups.empty() || 2 * (groups.back().size() + 1) > (size_t)cap) groups.emplace_back();
+            if (groups.empty() || 2 * (groups.back().size() + 1) > (size_t)cap ||
+                (b->pack_max && groups.back().size() >= b->pack_max))
+                groups.emplace_back();
             groups.back().push_back(i);
         }
         for (auto& g : groups) {
@@ -1302,7 +1305,7 @@ std::string batch_tune_key(const hsp_batch* b) {
     char hex[17];
     std::snprintf(hex, sizeof hex, "%016llx", (unsigned long long)h);
     const hsp_state* s0 = b->chains[0];
-    return "batch-v1 " + device_tag(s0->device, s0->num_cus) + " chains=" + std::to_string(b->chains.size()) +
+    return "batch-v2 " + device_tag(s0->device, s0->num_cus) + " chains=" + std::to_string(b->chains.size()) +
            " h=" + hex;
 }
 
@@ -1337,12 +1340,15 @@ hsp_status batch_tune(hsp_batch* b) {
     const std::string key = batch_tune_key(b);
     const char* path = tune_cache_path();
     std::string cached;
-    long mcg = 0, bwp = 0;
+    long mcg = 0, bwp = 0, pmax = 0;
     if (path && tune_cache_get(path, key, &cached) && tune_parse(cached, "mc_gz", &mcg) &&
-        tune_parse(cached, "bw", &bwp) && mcg >= 0 && mcg <= 65536 && bwp >= 10 && bwp <= 1000) {
+        tune_parse(cached, "bw", &bwp) && tune_parse(cached, "pack", &pmax) && mcg >= 0 && mcg <= 65536 &&
+        bwp >= 10 && bwp <= 1000 && pmax >= 0 && pmax <= 65536) {
         b->mc_gz = (uint32_t)mcg;
         b->bw_pct = (uint32_t)bwp;
-        b->plan_note = "mc_gz=" + std::to_string(mcg) + " bw=" + std::to_string(bwp) + " (cache)";
+        b->pack_max = (uint32_t)pmax;
+        b->plan_note = "mc_gz=" + std::to_string(mcg) + " bw=" + std::to_string(bwp) + " pack=" +
+                       std::to_string(pmax) + " (cache)";
         return HSP_OK;
     }
     std::vector<SavedChain> saved(b->chains.size());
@@ -1365,31 +1371,39 @@ hsp_status batch_tune(hsp_batch* b) {
     if (units)
         for (uint32_t m : {cus / 2, cus, 3 * cus / 2, 2 * cus, 3 * cus})
             if (m >= 1 && m <= units && std::find(mcs.begin(), mcs.end(), m) == mcs.end()) mcs.push_back(m);
+    // chains per pack: all that fit, or fewer chains each with more blocks
+    std::vector<uint32_t> pmaxs{0};
+    for (uint32_t m : {32u, 16u, 8u, 4u})
+        if (m < b->chains.size()) pmaxs.push_back(m);
     double best_ms = 1e300;
-    uint32_t best_mc = 0, best_bw = 100;
-    for (uint32_t mc : mcs)
-        for (uint32_t bw : {60u, 100u, 160u}) {
-            b->mc_gz = mc;
-            b->bw_pct = bw;
-            st = batch_build(b);
-            double ms = 0.0;
-            if (!st) st = time_batch(b, 1, 3, &ms);
-            free_packs(b);
-            if (st) return st;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best_mc = mc;
-                best_bw = bw;
+    uint32_t best_mc = 0, best_bw = 100, best_pm = 0;
+    for (uint32_t pm : pmaxs)
+        for (uint32_t mc : mcs)
+            for (uint32_t bw : {60u, 100u, 160u}) {
+                b->mc_gz = mc;
+                b->bw_pct = bw;
+                b->pack_max = pm;
+                st = batch_build(b);
+                double ms = 0.0;
+                if (!st) st = time_batch(b, 1, 3, &ms);
+                free_packs(b);
+                if (st) return st;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_mc = mc;
+                    best_bw = bw;
+                    best_pm = pm;
+                }
             }
-        }
     b->mc_gz = best_mc;
     b->bw_pct = best_bw;
+    b->pack_max = best_pm;
     for (size_t i = 0; i < b->chains.size(); ++i) {
         st = restore_chain(b->chains[i], saved[i]);
         if (st) return batch_fail(b, st, b->chains[i]->err);
     }
-    char buf[96];
-    std::snprintf(buf, sizeof buf, "mc_gz=%u bw=%u ms=%.4f", best_mc, best_bw, best_ms);
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "mc_gz=%u bw=%u pack=%u ms=%.4f", best_mc, best_bw, best_pm, best_ms);
     b->plan_note = std::string(buf) + " (measured)";
     if (path) (void)tune_cache_put(path, key, buf);
     return HSP_OK;
@@ -1906,6 +1920,7 @@ hsp_status hsp_get_plan(hsp_state* s, int64_t* group_blocks, int64_t* z_blocks, 
 hsp_status hsp_batch_get_plan(hsp_batch* b, int64_t* mc_blocks, int64_t* bw_pct, int64_t* packs, char* note,
                               int64_t note_cap) {
     if (!b) return HSP_EINVAL;
+    // pack_max is part of the note
     if (mc_blocks) *mc_blocks = b->mc_gz;
     if (bw_pct) *bw_pct = b->bw_pct;
     if (packs) *packs = (int64_t)b->packs.size();
