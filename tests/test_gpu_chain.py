@@ -56,28 +56,36 @@ def pooled(chains):
             np.sqrt(np.sum(np.square(se_v), 0)) / k)
 
 
-@pytest.mark.parametrize("which", ["n1000_p10", "n4000_p130"])
+@pytest.mark.parametrize("which", ["n1000_p10", "n4000_p130", "n100000_p100", "n100000_p100_bf16"])
 def test_long_chain_moments_agree_with_oracle(env, orc, which):
+    """GPU and oracle chains with independent seeds: the same posterior moments
+    within 4 MCSE.  The bfloat16 form is held to the oracle run on the
+    bfloat16-rounded design (the posterior it targets)."""
     torch, hsp = env
+    xt = "bf16" if which.endswith("bf16") else "f32"
     if which == "n1000_p10":
         d = synth.config1()
         n, chains = 3000, 4
-    else:
+    elif which == "n4000_p130":
         beta, _ = synth.sparse_beta(130, 5, 17, -2.0, 2.0)
         d = synth.probit_design(4000, 130, beta, 17, True)
         n, chains = 1500, 3
+    else:
+        d = synth.config2()
+        n, chains = 1200, 3
+    Xo = d.X if xt == "f32" else synth.bf16_bits(d.X).reshape(d.X.shape)
     burn = n // 5
-    G = orc.gram(d.X)
+    G = orc.gram(Xo)
     gpu, ora = [], []
     for c in range(chains):
         s = hsp.Sampler(torch.from_numpy(d.X).cuda(), torch.from_numpy(d.y).cuda(), seed=101 + c,
-                        max_draws=n)
+                        max_draws=n, x_type=xt)
         s.sweep(n)
         b, _, _ = s.draws()
         gpu.append(b[burn:])
         s.close()
         ch = orc.Chain(d.p)
-        bo, _ = ch.run(d.X, d.y, G, seed=201 + c, n=n)
+        bo, _ = ch.run(Xo, d.y, G, seed=201 + c, n=n)
         ora.append(bo[burn:])
     mg, smg, vg, svg = pooled(gpu)
     mo, smo, vo, svo = pooled(ora)
