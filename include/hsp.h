@@ -230,8 +230,10 @@ const char* hsp_last_error(const hsp_state* s);
  * chains of one design share its library copy of X, y and G = X^T X).  One
  * hsp_batch_sweep advances every chain by the same number of sweeps; each
  * batched sweep is a single replay of a captured HIP graph holding every
- * chain's sweep kernel, one after another on the batch's stream (every
- * dataset of a batch is resident: x_stream is ignored).  Chain i
+ * chain's sweep kernel, one after another on the batch's stream (the
+ * multi-chain passes described below may run on a second stream beside the
+ * other chains' launches; the graph joins it before their p-side launch).
+ * Every dataset of a batch is resident (x_stream is ignored).  Chain i
  * (dataset-major order) uses Philox counter word 3 = opt->chain_id + i, so it
  * draws exactly what a lone sampler created with that chain id draws --
  * except chains that share a bfloat16 design under multi_chain_z: their

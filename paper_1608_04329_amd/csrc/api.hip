@@ -996,6 +996,9 @@ struct hsp_batch {
     uint32_t mc_gz = 0;        // blocks of each multi-chain z pass (0: two per compute unit)
     uint32_t bw_pct = 100;     // pack split model: z-pass bandwidth per block, percent of nominal
     uint32_t pack_max = 0;     // most chains per pack (0: as many as the resident blocks allow)
+    bool overlap = true;       // multi-chain passes on a second stream, beside the other packs
+    hipStream_t side = nullptr;  // that stream (captured into the graph only)
+    hipEvent_t fork = nullptr, join = nullptr;
     bool autotune = false;
     std::string plan_note = "built-in";
 };
@@ -1023,6 +1026,9 @@ void free_packs(hsp_batch* b) {
 void free_batch(hsp_batch* b) {
     if (!b) return;
     free_packs(b);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
+    if (b->side) (void)hipStreamDestroy(b->side);
     b->timer.reset();
     for (auto it = b->chains.rbegin(); it != b->chains.rend(); ++it) free_state(*it);  // borrowers first
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -1267,12 +1273,43 @@ hsp_status batch_build(hsp_batch* b) {
         if (st != HSP_OK) return st;
     }
     if (b->graph) return HSP_OK;
+    bool any_mc = false, any_plain = false;
+    for (const Pack& pk : b->packs) (pk.mc ? any_mc : any_plain) = true;
+    const bool overlap = b->overlap && any_mc && any_plain;
+    hipError_t e = hipSuccess;
+    if (overlap && !b->side) {
+        e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+        if (!e) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        if (!e) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+        if (e) return batch_fail(b, HSP_EHIP, std::string("batch side stream: ") + hipGetErrorString(e));
+    }
     hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-    for (size_t i = 0; !e && i < b->packs.size(); ++i) {
-        const Pack& pk = b->packs[i];
-        if (pk.mc) e = mc_launch(pk.dmc, pk.mc_ld, pk.mc_gz, b->stream);
-        if (!e) e = pack_launch(pk.xtype, pk.chunks, pk.dtab, pk.dmap, pk.blocks, b->stream);
+    e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (overlap) {
+        // The multi-chain passes wait on nothing, so they may run beside the
+        // other packs (whose blocks then become resident as they finish); the
+        // launches that wait inside (the packs, and the p-side launch of the
+        // multi-chain chains) stay one after another on the batch's stream.
+        if (!e) e = hipEventRecord(b->fork, b->stream);
+        if (!e) e = hipStreamWaitEvent(b->side, b->fork, 0);
+        for (size_t i = 0; !e && i < b->packs.size(); ++i)
+            if (b->packs[i].mc) e = mc_launch(b->packs[i].dmc, b->packs[i].mc_ld, b->packs[i].mc_gz, b->side);
+        if (!e) e = hipEventRecord(b->join, b->side);
+        for (size_t i = 0; !e && i < b->packs.size(); ++i) {
+            const Pack& pk = b->packs[i];
+            if (!pk.mc) e = pack_launch(pk.xtype, pk.chunks, pk.dtab, pk.dmap, pk.blocks, b->stream);
+        }
+        if (!e) e = hipStreamWaitEvent(b->stream, b->join, 0);
+        for (size_t i = 0; !e && i < b->packs.size(); ++i) {
+            const Pack& pk = b->packs[i];
+            if (pk.mc) e = pack_launch(pk.xtype, pk.chunks, pk.dtab, pk.dmap, pk.blocks, b->stream);
+        }
+    } else {
+        for (size_t i = 0; !e && i < b->packs.size(); ++i) {
+            const Pack& pk = b->packs[i];
+            if (pk.mc) e = mc_launch(pk.dmc, pk.mc_ld, pk.mc_gz, b->stream);
+            if (!e) e = pack_launch(pk.xtype, pk.chunks, pk.dtab, pk.dmap, pk.blocks, b->stream);
+        }
     }
     hipError_t e2 = hipStreamEndCapture(b->stream, &g);
     if (!e) e = e2;
@@ -1305,7 +1342,7 @@ std::string batch_tune_key(const hsp_batch* b) {
     char hex[17];
     std::snprintf(hex, sizeof hex, "%016llx", (unsigned long long)h);
     const hsp_state* s0 = b->chains[0];
-    return "batch-v2 " + device_tag(s0->device, s0->num_cus) + " chains=" + std::to_string(b->chains.size()) +
+    return "batch-v3 " + device_tag(s0->device, s0->num_cus) + " chains=" + std::to_string(b->chains.size()) +
            " h=" + hex;
 }
 
@@ -1340,15 +1377,16 @@ hsp_status batch_tune(hsp_batch* b) {
     const std::string key = batch_tune_key(b);
     const char* path = tune_cache_path();
     std::string cached;
-    long mcg = 0, bwp = 0, pmax = 0;
+    long mcg = 0, bwp = 0, pmax = 0, ov = 1;
     if (path && tune_cache_get(path, key, &cached) && tune_parse(cached, "mc_gz", &mcg) &&
-        tune_parse(cached, "bw", &bwp) && tune_parse(cached, "pack", &pmax) && mcg >= 0 && mcg <= 65536 &&
-        bwp >= 10 && bwp <= 1000 && pmax >= 0 && pmax <= 65536) {
+        tune_parse(cached, "bw", &bwp) && tune_parse(cached, "pack", &pmax) && tune_parse(cached, "ov", &ov) &&
+        mcg >= 0 && mcg <= 65536 && bwp >= 10 && bwp <= 1000 && pmax >= 0 && pmax <= 65536 && (ov == 0 || ov == 1)) {
         b->mc_gz = (uint32_t)mcg;
         b->bw_pct = (uint32_t)bwp;
         b->pack_max = (uint32_t)pmax;
+        b->overlap = ov != 0;
         b->plan_note = "mc_gz=" + std::to_string(mcg) + " bw=" + std::to_string(bwp) + " pack=" +
-                       std::to_string(pmax) + " (cache)";
+                       std::to_string(pmax) + " ov=" + std::to_string(ov) + " (cache)";
         return HSP_OK;
     }
     std::vector<SavedChain> saved(b->chains.size());
@@ -1398,12 +1436,28 @@ hsp_status batch_tune(hsp_batch* b) {
     b->mc_gz = best_mc;
     b->bw_pct = best_bw;
     b->pack_max = best_pm;
+    bool best_ov = true;
+    {
+        // the passes beside the packs, or all launches one after another
+        b->overlap = false;
+        st = batch_build(b);
+        double ms = 0.0;
+        if (!st) st = time_batch(b, 1, 3, &ms);
+        free_packs(b);
+        if (st) return st;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_ov = false;
+        }
+        b->overlap = best_ov;
+    }
     for (size_t i = 0; i < b->chains.size(); ++i) {
         st = restore_chain(b->chains[i], saved[i]);
         if (st) return batch_fail(b, st, b->chains[i]->err);
     }
     char buf[128];
-    std::snprintf(buf, sizeof buf, "mc_gz=%u bw=%u pack=%u ms=%.4f", best_mc, best_bw, best_pm, best_ms);
+    std::snprintf(buf, sizeof buf, "mc_gz=%u bw=%u pack=%u ov=%d ms=%.4f", best_mc, best_bw, best_pm, (int)best_ov,
+                  best_ms);
     b->plan_note = std::string(buf) + " (measured)";
     if (path) (void)tune_cache_put(path, key, buf);
     return HSP_OK;

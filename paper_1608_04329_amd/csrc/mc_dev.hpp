@@ -155,8 +155,14 @@ __device__ void mc_role(McView& m, uint32_t rank, double* lds) {
     uint32_t maxatt = 0;
     bool capped = false, wrote = false;
 
+    // tile t's X (16-byte loads) and the outcome of the row this thread draws
     U32x4 xr[KS];
+    uint32_t ypre = 0;
     auto load_tile = [&](uint32_t t) {
+        {
+            const uint32_t yr = t * kMcRows + (threadIdx.x >> 4);
+            ypre = yr < N ? (uint32_t)m.y[yr] : 0u;
+        }
         const uint32_t row = t * kMcRows + (uint32_t)n;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
@@ -214,6 +220,7 @@ __device__ void mc_role(McView& m, uint32_t rank, double* lds) {
         for (uint32_t t = t0; t < t1; ++t) {
             // X beta for the 16 chains, and the transposed tile
             F32x4 de = {0.0f, 0.0f, 0.0f, 0.0f};
+            const uint32_t ycur = ypre;
             Bf16x4 tt[KS][2];
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
@@ -240,7 +247,7 @@ __device__ void mc_role(McView& m, uint32_t rank, double* lds) {
             float eta = 0.0f;
 #pragma unroll
             for (int w = 0; w < kWPB; ++w) eta += red[(w * kMcRows + mrow) * kMcChains + n];
-            const float ys = (active && m.y[row]) ? 1.0f : -1.0f;
+            const float ys = (active && ycur) ? 1.0f : -1.0f;
             const float mu = ys * eta;
             const bool gauss = mu > 0.47f;
             const float den = sqrtf(fmaf(mu, mu, 4.0f)) - mu;
