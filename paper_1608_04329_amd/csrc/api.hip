@@ -981,6 +981,13 @@ struct Pack {
     const SweepArgs** dtab = nullptr;       // pointers to them (device)
     uint16_t* dmap = nullptr;               // block -> chain within the pack (device)
     std::vector<uint32_t*> sched;           // per-chain task lists and bounds for its gp (device)
+    // a shared z queue: the chains have no z blocks of their own; `workers`
+    // blocks after every p-side group take all their z passes
+    bool queue = false;
+    uint32_t workers = 0;
+    std::vector<uint32_t> home;             // home chain of each worker (pack-local index)
+    std::vector<uint32_t> unit_tiles;       // row tiles per unit of each chain
+    PackQ* dq = nullptr;                    // the queue's counters (device)
 };
 
 struct hsp_batch {
@@ -996,6 +1003,8 @@ struct hsp_batch {
     uint32_t mc_gz = 0;        // blocks of each multi-chain z pass (0: two per compute unit)
     uint32_t bw_pct = 100;     // pack split model: z-pass bandwidth per block, percent of nominal
     uint32_t pack_max = 0;     // most chains per pack (0: as many as the resident blocks allow)
+    uint32_t zq_kib = 64;      // packs of row-per-wave chains share one z queue, units of about this
+                               // many KiB of X (0: every chain has z blocks of its own)
     bool overlap = true;       // multi-chain passes on a second stream, beside the other packs
     hipStream_t side = nullptr;  // that stream (captured into the graph only)
     hipEvent_t fork = nullptr, join = nullptr;
@@ -1017,6 +1026,7 @@ void free_packs(hsp_batch* b) {
         if (pk.dargs) (void)hipFree(pk.dargs);
         if (pk.dtab) (void)hipFree(pk.dtab);
         if (pk.dmap) (void)hipFree(pk.dmap);
+        if (pk.dq) (void)hipFree(pk.dq);
         for (uint32_t* q : pk.sched)
             if (q) (void)hipFree(q);
     }
@@ -1069,6 +1079,55 @@ uint32_t count_tasks(uint32_t nt) {
         n += 1 + m + k + m * (m + 1) / 2 + m * (k + 1);
     }
     return n;
+}
+
+// Blocks of a queue pack: one p-side block per chain, and more for the chain
+// whose factorisation is predicted to take longest while that outlasts the
+// z passes on the remaining worker blocks; the workers' home chains in
+// proportion to the chains' bytes of X; each chain's unit of about zq_kib KiB
+// of rows (whole row tiles).
+void plan_queue_pack(const hsp_batch* b, Pack& pk, const std::vector<ChainCost>& cost, int cap, double bw,
+                     int rows) {
+    const size_t nc = pk.chains.size();
+    pk.queue = true;
+    pk.gp.assign(nc, 1);
+    pk.gz.assign(nc, 0);
+    double bytes = 0.0;
+    for (size_t j = 0; j < nc; ++j) bytes += cost[pk.chains[j]].bytes;
+    uint32_t used = (uint32_t)nc;
+    while (used + 1 < (uint32_t)cap) {
+        const double tz = bytes / ((double)(cap - used) * bw);
+        size_t worst = nc;
+        double tw = -1.0;
+        for (size_t j = 0; j < nc; ++j) {
+            const ChainCost& c = cost[pk.chains[j]];
+            const double tp = p_time_us(c, pk.gp[j]);
+            if (pk.gp[j] < c.gp_max && tp > tw) {
+                tw = tp;
+                worst = j;
+            }
+        }
+        if (worst == nc || tw <= tz) break;
+        ++pk.gp[worst];
+        ++used;
+    }
+    pk.workers = (uint32_t)cap - used;
+    pk.blocks = (uint32_t)cap;
+    pk.home.resize(pk.workers);
+    double acc = 0.0;
+    size_t j = 0;
+    for (uint32_t w = 0; w < pk.workers; ++w) {
+        const double at = (w + 0.5) * bytes / pk.workers;
+        while (j + 1 < nc && acc + cost[pk.chains[j]].bytes <= at) acc += cost[pk.chains[j++]].bytes;
+        pk.home[w] = (uint32_t)j;
+    }
+    pk.unit_tiles.resize(nc);
+    for (size_t i = 0; i < nc; ++i) {
+        const hsp_state* s = b->chains[pk.chains[i]];
+        const double tile_bytes = (double)rows * s->x.ld * (s->x.xtype == 0 ? 4 : 2);
+        const double want = std::ceil(b->zq_kib * 1024.0 / tile_bytes);
+        pk.unit_tiles[i] = (uint32_t)std::min<double>(kZUnitMax, std::max(1.0, want));
+    }
 }
 
 // Split the chains into packs that fit the device's resident capacity, and
@@ -1166,11 +1225,17 @@ hsp_status plan_packs(hsp_batch* b) {
                 groups.emplace_back();
             groups.back().push_back(i);
         }
+        const bool queue = b->zq_kib > 0 && key[2] == 0;
         for (auto& g : groups) {
             Pack pk;
             pk.xtype = xt;
             pk.chunks = chunks;
             pk.chains = g;
+            if (queue && g.size() <= (size_t)kPackQMax) {
+                plan_queue_pack(b, pk, cost, cap, bw, rows);
+                b->packs.push_back(std::move(pk));
+                continue;
+            }
             pk.gp.assign(g.size(), 1);
             pk.gz.assign(g.size(), 1);
             uint32_t used = 2 * (uint32_t)g.size();
@@ -1209,6 +1274,12 @@ hsp_status plan_packs(hsp_batch* b) {
         std::vector<SweepArgs> host(nc);
         std::vector<const SweepArgs*> tab(nc);
         std::vector<uint16_t> map(pk.blocks);
+        PackQ hq{};
+        if (pk.queue) {
+            if (dalloc(&pk.dq, 1)) return batch_fail(b, HSP_ENOMEM, "pack allocation failed");
+            hq.nchains = (uint32_t)nc;
+            hq.workers = pk.workers;
+        }
         uint32_t blk = 0;
         for (size_t j = 0; j < nc; ++j) {
             hsp_state* s = b->chains[pk.chains[j]];
@@ -1219,6 +1290,14 @@ hsp_status plan_packs(hsp_batch* b) {
             h.z_static_pct = kZStaticPctDefault;
             h.z_unit = kZUnitDefault;
             h.zgroups = (h.gz + kZGroup - 1) / kZGroup;
+            if (pk.queue) {
+                // the p-side waits for the chain's units instead of its groups
+                const uint32_t tiles = (s->x.N + rows_for(pk.xtype, pk.chunks) - 1) / rows_for(pk.xtype, pk.chunks);
+                h.z_unit = pk.unit_tiles[j];
+                hq.units[j] = (tiles + h.z_unit - 1) / h.z_unit;
+                h.zgroups = hq.units[j];
+                h.zq = dev_ptr(pk.dq);
+            }
             h.block0 = blk;
             if (s->x.p > (uint32_t)kSmallP) {
                 const uint32_t nt = (s->x.p + kTile - 1) / kTile;
@@ -1240,6 +1319,14 @@ hsp_status plan_packs(hsp_batch* b) {
             for (uint32_t q = 0; q < h.gp + h.gz; ++q) map[blk + q] = (uint16_t)j;
             blk += h.gp + h.gz;
         }
+        if (pk.queue) {
+            // the workers follow every p-side group
+            for (uint32_t w = 0; w < pk.workers; ++w) map[blk + w] = (uint16_t)(kWorkerBit | pk.home[w]);
+            blk += pk.workers;
+            if (hipMemcpy(pk.dq, &hq, sizeof hq, hipMemcpyHostToDevice))
+                return batch_fail(b, HSP_EHIP, "pack upload");
+        }
+        if (blk != pk.blocks) return batch_fail(b, HSP_EHIP, "pack block map does not cover the launch");
         if (hipMemcpy(pk.dargs, host.data(), nc * sizeof(SweepArgs), hipMemcpyHostToDevice) ||
             hipMemcpy(pk.dtab, tab.data(), nc * sizeof(const SweepArgs*), hipMemcpyHostToDevice) ||
             hipMemcpy(pk.dmap, map.data(), map.size() * 2, hipMemcpyHostToDevice))
@@ -1342,7 +1429,7 @@ std::string batch_tune_key(const hsp_batch* b) {
     char hex[17];
     std::snprintf(hex, sizeof hex, "%016llx", (unsigned long long)h);
     const hsp_state* s0 = b->chains[0];
-    return "batch-v3 " + device_tag(s0->device, s0->num_cus) + " chains=" + std::to_string(b->chains.size()) +
+    return "batch-v4 " + device_tag(s0->device, s0->num_cus) + " chains=" + std::to_string(b->chains.size()) +
            " h=" + hex;
 }
 
@@ -1369,24 +1456,28 @@ hsp_status time_batch(hsp_batch* b, int warm, int timed, double* ms) {
     return HSP_OK;
 }
 
-// The autotuner for a batch: blocks of each multi-chain z pass and the
-// bandwidth the pack split model gives a z-pass block, by timing a few
-// batched sweeps of every candidate (or from the cache).  Every chain's
-// state is put back afterwards.
+// The autotuner for a batch: blocks of each multi-chain z pass, chains per
+// pack, the bandwidth the pack split model gives a z-pass block, whether the
+// packs share one z queue (and its unit size) and whether the multi-chain
+// passes run beside the other packs, by timing a few batched sweeps of every
+// candidate (or from the cache).  Every chain's state is put back afterwards.
 hsp_status batch_tune(hsp_batch* b) {
     const std::string key = batch_tune_key(b);
     const char* path = tune_cache_path();
     std::string cached;
-    long mcg = 0, bwp = 0, pmax = 0, ov = 1;
+    long mcg = 0, bwp = 0, pmax = 0, ov = 1, zq = 0;
     if (path && tune_cache_get(path, key, &cached) && tune_parse(cached, "mc_gz", &mcg) &&
         tune_parse(cached, "bw", &bwp) && tune_parse(cached, "pack", &pmax) && tune_parse(cached, "ov", &ov) &&
-        mcg >= 0 && mcg <= 65536 && bwp >= 10 && bwp <= 1000 && pmax >= 0 && pmax <= 65536 && (ov == 0 || ov == 1)) {
+        tune_parse(cached, "zq", &zq) && mcg >= 0 && mcg <= 65536 && bwp >= 10 && bwp <= 1000 && pmax >= 0 &&
+        pmax <= 65536 && (ov == 0 || ov == 1) && zq >= 0 && zq <= 4096) {
         b->mc_gz = (uint32_t)mcg;
         b->bw_pct = (uint32_t)bwp;
         b->pack_max = (uint32_t)pmax;
         b->overlap = ov != 0;
+        b->zq_kib = (uint32_t)zq;
         b->plan_note = "mc_gz=" + std::to_string(mcg) + " bw=" + std::to_string(bwp) + " pack=" +
-                       std::to_string(pmax) + " ov=" + std::to_string(ov) + " (cache)";
+                       std::to_string(pmax) + " ov=" + std::to_string(ov) + " zq=" + std::to_string(zq) +
+                       " (cache)";
         return HSP_OK;
     }
     std::vector<SavedChain> saved(b->chains.size());
@@ -1414,28 +1505,44 @@ hsp_status batch_tune(hsp_batch* b) {
     for (uint32_t m : {32u, 16u, 8u, 4u})
         if (m < b->chains.size()) pmaxs.push_back(m);
     double best_ms = 1e300;
-    uint32_t best_mc = 0, best_bw = 100, best_pm = 0;
-    for (uint32_t pm : pmaxs)
+    uint32_t best_mc = 0, best_bw = 100, best_pm = 0, best_zq = 0;
+    auto trial = [&](uint32_t pm, uint32_t mc, uint32_t bw, uint32_t zq) -> hsp_status {
+        b->mc_gz = mc;
+        b->bw_pct = bw;
+        b->pack_max = pm;
+        b->zq_kib = zq;
+        hsp_status s2 = batch_build(b);
+        double ms = 0.0;
+        if (!s2) s2 = time_batch(b, 1, 3, &ms);
+        free_packs(b);
+        if (s2) return s2;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_mc = mc;
+            best_bw = bw;
+            best_pm = pm;
+            best_zq = zq;
+        }
+        return HSP_OK;
+    };
+    // a shared z queue per pack: its unit size, blocks per multi-chain pass
+    // and chains per pack
+    for (uint32_t zq : {32u, 64u, 128u})
         for (uint32_t mc : mcs)
-            for (uint32_t bw : {60u, 100u, 160u}) {
-                b->mc_gz = mc;
-                b->bw_pct = bw;
-                b->pack_max = pm;
-                st = batch_build(b);
-                double ms = 0.0;
-                if (!st) st = time_batch(b, 1, 3, &ms);
-                free_packs(b);
-                if (st) return st;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best_mc = mc;
-                    best_bw = bw;
-                    best_pm = pm;
-                }
-            }
+            for (uint32_t pm : {0u, 32u})
+                if ((pm == 0 || pm < b->chains.size()) && (st = trial(pm, mc, 100, zq)) != HSP_OK) return st;
+    // chains with z blocks of their own: chains per pack and the split
+    // model's bandwidth, with the best pass size so far or the built-in one
+    std::vector<uint32_t> mc_c{best_mc};
+    if (best_mc != 0) mc_c.push_back(0);
+    for (uint32_t mc : mc_c)
+        for (uint32_t pm : pmaxs)
+            for (uint32_t bw : {60u, 100u, 160u})
+                if ((st = trial(pm, mc, bw, 0)) != HSP_OK) return st;
     b->mc_gz = best_mc;
     b->bw_pct = best_bw;
     b->pack_max = best_pm;
+    b->zq_kib = best_zq;
     bool best_ov = true;
     {
         // the passes beside the packs, or all launches one after another
@@ -1456,8 +1563,8 @@ hsp_status batch_tune(hsp_batch* b) {
         if (st) return batch_fail(b, st, b->chains[i]->err);
     }
     char buf[128];
-    std::snprintf(buf, sizeof buf, "mc_gz=%u bw=%u pack=%u ov=%d ms=%.4f", best_mc, best_bw, best_pm, (int)best_ov,
-                  best_ms);
+    std::snprintf(buf, sizeof buf, "mc_gz=%u bw=%u pack=%u ov=%d zq=%u ms=%.4f", best_mc, best_bw, best_pm,
+                  (int)best_ov, best_zq, best_ms);
     b->plan_note = std::string(buf) + " (measured)";
     if (path) (void)tune_cache_put(path, key, buf);
     return HSP_OK;
@@ -1979,6 +2086,16 @@ hsp_status hsp_batch_get_plan(hsp_batch* b, int64_t* mc_blocks, int64_t* bw_pct,
     if (bw_pct) *bw_pct = b->bw_pct;
     if (packs) *packs = (int64_t)b->packs.size();
     if (note && note_cap > 0) std::snprintf(note, (size_t)note_cap, "%s", b->plan_note.c_str());
+    return HSP_OK;
+}
+
+hsp_status hsp_batch_set_zqueue(hsp_batch* b, int32_t kib) {
+    if (!b) return HSP_EINVAL;
+    if (kib < 0 || kib > 4096) return batch_fail(b, HSP_EINVAL, "kib must lie in [0, 4096]");
+    free_packs(b);  // planned again at the next sweep
+    b->zq_kib = (uint32_t)kib;
+    b->autotune = false;
+    b->plan_note = "zq=" + std::to_string(kib) + " (set)";
     return HSP_OK;
 }
 

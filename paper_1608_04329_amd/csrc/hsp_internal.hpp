@@ -124,6 +124,8 @@ struct XLayout {
     uint32_t ld;
 };
 
+struct PackQ;
+
 // Everything one launch of the sweep kernel touches.
 struct SweepArgs {
     XLayout x;
@@ -169,6 +171,27 @@ struct SweepArgs {
     uint32_t first_row;      // global index of x.X's first row (X streamed in row chunks; else 0):
                              // y, the Philox counters and the debug outputs use global rows
     HSP_GLOBAL const uint32_t* row_id;  // original index of each stored row (rows reordered), or null
+    HSP_GLOBAL PackQ* zq;  // the pack's shared z queue, or null (then gz blocks of its own)
+};
+
+// ---- the shared z queue of a pack -----------------------------------------------
+// A pack may give its chains no z-pass blocks of their own: its worker
+// blocks then take every chain's z pass from one queue.  Chain c's rows are
+// cut into units[c] units of z_unit row tiles, claimed from next[c]; a worker
+// drains the units of its home chain first, then those of whichever chain
+// has most left.  When a worker leaves a chain it adds its float64 tile sums
+// into the chain's b accumulator (exact on the 2^-24 grid, so the order of
+// the additions does not matter) and then the number of units it finished
+// into the chain's z_count, which the chain's p-side waits to reach
+// zgroups = units[c].  A chain's draws are those of the chain alone.
+constexpr int kPackQMax = 256;             // chains of a queue pack
+constexpr uint16_t kWorkerBit = 0x8000u;   // block map: a worker of the queue (low bits: home chain)
+struct PackQ {
+    uint32_t nchains;
+    uint32_t workers;                         // worker blocks of the launch
+    alignas(128) uint32_t done;               // workers finished (zero between launches)
+    alignas(128) uint32_t next[kPackQMax];    // next unit of each chain (zero between launches)
+    alignas(128) uint32_t units[kPackQMax];   // units of each chain
 };
 
 // Device view of a launch description.

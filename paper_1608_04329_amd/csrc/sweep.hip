@@ -27,7 +27,8 @@ namespace {
 // pinned in scalar registers for the whole kernel.
 // A launch may serve several independent chains (a batch): block b belongs
 // to chain chain_of_block[b] (chain 0 for all when the map is null) and runs
-// that chain's role at position b - block0 of its blocks.
+// that chain's role at position b - block0 of its blocks, or, marked with
+// kWorkerBit, is a worker of the pack's shared z queue.
 template <int XT, int KC, int R, bool WIDE>
 __device__ __forceinline__ void run_block(Args& a, double* lds) {
     const uint32_t b = blockIdx.x - a.block0;
@@ -43,6 +44,12 @@ __global__ __launch_bounds__(kThreads, 2) void sweep_kernel(const SweepArgs* con
                                                             const uint16_t* __restrict__ chain_of_block) {
     __shared__ double lds[kLdsDoubles];
     const uint32_t c = chain_of_block ? chain_of_block[blockIdx.x] : 0u;
+    if constexpr (!WIDE) {
+        if (c & kWorkerBit) {
+            zqueue_role<XT, KC, R>(args, c & ~(uint32_t)kWorkerBit, lds);
+            return;
+        }
+    }
     run_block<XT, KC, R, WIDE>(*(Args*)args[c], lds);
 }
 

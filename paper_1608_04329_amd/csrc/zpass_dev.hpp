@@ -89,6 +89,145 @@ __device__ __forceinline__ void tn_candidate(float mu, bool gauss, float theta, 
     acc = gauss ? (tg > 0.0f) : (ub < rho);
 }
 
+// One tile of R rows of chain a (rows t R ..): eta = x_i beta (with wide
+// rows, the block's four quarters added through LDS), the truncated-normal
+// draws, and the tile's grid-rounded sums of x_ij z_i added into bacc.  bl
+// holds beta (column-scaled, float32) on this lane's columns.
+template <int XT, int KC, int R, bool WIDE>
+__device__ __forceinline__ void z_tile(Args& a, uint32_t t, uint32_t ksweep,
+                                       const float (&bl)[KC][XTraits<XT>::VEC],
+                                       double (&bacc)[KC][XTraits<XT>::VEC], uint32_t& maxatt, bool& capped,
+                                       uint32_t& parity, double* eta_lds) {
+    constexpr int VEC = XTraits<XT>::VEC;
+    constexpr int EB = XTraits<XT>::BYTES;
+    constexpr int CW = kWave * VEC;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const uint32_t ld = a.x.ld;
+    const uint32_t N = a.x.N;
+    const char* __restrict__ Xb = static_cast<const char*>(a.x.X);
+    const size_t row_bytes = (size_t)ld * EB;
+    const uint32_t c0 = WIDE ? (uint32_t)wave * KC * CW : 0u;
+    const uint32_t row0 = t * R;
+    uint4 xr[R][KC];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            const uint32_t row = row0 + r;
+            const uint32_t col = c0 + kc * CW + lane * VEC;
+            if (row < N && col < ld) {
+#if HSP_X_NONTEMPORAL
+                const U32x4 v = __builtin_nontemporal_load(
+                    reinterpret_cast<const U32x4*>(Xb + row * row_bytes + (size_t)col * EB));
+                xr[r][kc] = make_uint4(v.x, v.y, v.z, v.w);
+#else
+                xr[r][kc] = *reinterpret_cast<const uint4*>(Xb + row * row_bytes + (size_t)col * EB);
+#endif
+            } else
+                xr[r][kc] = make_uint4(0u, 0u, 0u, 0u);
+        }
+
+    // eta for the R rows of the tile, reduced across the wave
+    float s[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc = fmaf(xelem<XT>(xr[r][kc], e), bl[kc][e], acc);
+        s[r] = acc;
+    }
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1)
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[r] += __shfl_xor(s[r], off);
+    if constexpr (WIDE) {
+        // the four quarters' sums through LDS, added in wave order; the
+        // two slots alternate, so one barrier per tile keeps a slot from
+        // being rewritten before every wave has read it
+        double* slotp = eta_lds + parity * (kWPB * R);
+        if (lane == 0)
+#pragma unroll
+            for (int r = 0; r < R; ++r) slotp[wave * R + r] = (double)s[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float v = (float)slotp[r];
+#pragma unroll
+            for (int w = 1; w < kWPB; ++w) v += (float)slotp[w * R + r];
+            s[r] = v;
+        }
+        parity ^= 1u;
+    }
+    float eta = s[0];
+#pragma unroll
+    for (int r = 1; r < R; ++r) eta = (lane == r) ? s[r] : eta;
+
+    // lane r < R draws z for row row0 + r: position first_row + row0 + r of
+    // the stored X and y (X may arrive in row chunks), whose original row
+    // index (the rows may have been reordered) sets its Philox counters
+    // and its place in the debug outputs
+    const uint32_t row = row0 + (uint32_t)lane;
+    const bool active = lane < R && row < N;
+    const uint32_t pos = a.first_row + row;
+    const uint32_t grow = active ? (a.row_id ? a.row_id[pos] : pos) : 0u;
+    const float ys = (active && a.y[pos]) ? 1.0f : -1.0f;
+    const float mu = ys * eta;
+    const bool gauss = mu > 0.47f;
+    const float den = sqrtf(fmaf(mu, mu, 4.0f)) - mu;  // 2 theta
+    const float theta = 0.5f * den;
+    const float inv_theta = 2.0f / den;
+    float zval = 0.0f;
+    int32_t att = -1;
+    bool done = !active;
+    for (uint32_t round = 0; __ballot(!done) != 0ull; ++round) {
+        if (!done) {
+            const Words4 w = draw_words(a.seed, grow, ksweep, kTagZ, round, a.chain);
+            float t0, t1;
+            bool a0, a1;
+            tn_candidate(mu, gauss, theta, inv_theta, u01f(w.w0), u01f(w.w1), t0, a0);
+            tn_candidate(mu, gauss, theta, inv_theta, u01f(w.w2), u01f(w.w3), t1, a1);
+            if (a0) {
+                zval = ys * t0;
+                att = (int32_t)(2 * round);
+                done = true;
+            } else if (a1) {
+                zval = ys * t1;
+                att = (int32_t)(2 * round + 1);
+                done = true;
+            } else if (round + 1 >= kMaxRounds) {
+                zval = __builtin_nanf("");
+                done = true;
+                capped = true;
+            }
+        }
+    }
+    if (active && (!WIDE || wave == 0)) {
+        maxatt = max(maxatt, (uint32_t)(att + 1));
+        if (a.zdbg) {
+            a.zdbg[grow] = zval;
+            a.adbg[grow] = att | (gauss ? (1 << 30) : 0);
+        }
+    }
+
+    // b += x_r^T z_r for the tile: R-term float sums, then float64
+    float zr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        zr[r] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zval), r));
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc = fmaf(zr[r], xelem<XT>(xr[r][kc], e), acc);
+            bacc[kc][e] += on_grid((double)acc);
+        }
+}
+
 // The z-pass role of the sweep kernel: block zrank of nz z-pass blocks.
 // Short rows (WIDE false, see wide_chunks): each wave holds whole rows,
 // KC chunks per lane, and takes tiles on its own.  Wider rows (WIDE): the
@@ -101,15 +240,12 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
                                            uint32_t ksweep, double* red) {
     if (zrank >= nz) return;  // no z-pass work in this launch
     constexpr int VEC = XTraits<XT>::VEC;
-    constexpr int EB = XTraits<XT>::BYTES;
     constexpr int CW = kWave * VEC;  // columns covered by one wave-wide 16-byte load
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const uint32_t ld = a.x.ld;
     const uint32_t N = a.x.N;
-    const char* __restrict__ Xb = static_cast<const char*>(a.x.X);
-    const size_t row_bytes = (size_t)ld * EB;
     const uint32_t c0 = WIDE ? (uint32_t)wave * KC * CW : 0u;  // first column of this wave's part
 
     float bl[KC][VEC];
@@ -132,124 +268,7 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
     double* eta_lds = red + 8;          // [2][kWPB][R], after the unit slot
 
     auto tile = [&](uint32_t t) {
-        const uint32_t row0 = t * R;
-        uint4 xr[R][KC];
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int kc = 0; kc < KC; ++kc) {
-                const uint32_t row = row0 + r;
-                const uint32_t col = c0 + kc * CW + lane * VEC;
-                if (row < N && col < ld) {
-#if HSP_X_NONTEMPORAL
-                    const U32x4 v = __builtin_nontemporal_load(
-                        reinterpret_cast<const U32x4*>(Xb + row * row_bytes + (size_t)col * EB));
-                    xr[r][kc] = make_uint4(v.x, v.y, v.z, v.w);
-#else
-                    xr[r][kc] = *reinterpret_cast<const uint4*>(Xb + row * row_bytes + (size_t)col * EB);
-#endif
-                } else
-                    xr[r][kc] = make_uint4(0u, 0u, 0u, 0u);
-            }
-
-        // eta for the R rows of the tile, reduced across the wave
-        float s[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            float acc = 0.0f;
-#pragma unroll
-            for (int kc = 0; kc < KC; ++kc)
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) acc = fmaf(xelem<XT>(xr[r][kc], e), bl[kc][e], acc);
-            s[r] = acc;
-        }
-#pragma unroll
-        for (int off = kWave / 2; off >= 1; off >>= 1)
-#pragma unroll
-            for (int r = 0; r < R; ++r) s[r] += __shfl_xor(s[r], off);
-        if constexpr (WIDE) {
-            // the four quarters' sums through LDS, added in wave order; the
-            // two slots alternate, so one barrier per tile keeps a slot from
-            // being rewritten before every wave has read it
-            double* slotp = eta_lds + parity * (kWPB * R);
-            if (lane == 0)
-#pragma unroll
-                for (int r = 0; r < R; ++r) slotp[wave * R + r] = (double)s[r];
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                float v = (float)slotp[r];
-#pragma unroll
-                for (int w = 1; w < kWPB; ++w) v += (float)slotp[w * R + r];
-                s[r] = v;
-            }
-            parity ^= 1u;
-        }
-        float eta = s[0];
-#pragma unroll
-        for (int r = 1; r < R; ++r) eta = (lane == r) ? s[r] : eta;
-
-        // lane r < R draws z for row row0 + r: position first_row + row0 + r of
-        // the stored X and y (X may arrive in row chunks), whose original row
-        // index (the rows may have been reordered) sets its Philox counters
-        // and its place in the debug outputs
-        const uint32_t row = row0 + (uint32_t)lane;
-        const bool active = lane < R && row < N;
-        const uint32_t pos = a.first_row + row;
-        const uint32_t grow = active ? (a.row_id ? a.row_id[pos] : pos) : 0u;
-        const float ys = (active && a.y[pos]) ? 1.0f : -1.0f;
-        const float mu = ys * eta;
-        const bool gauss = mu > 0.47f;
-        const float den = sqrtf(fmaf(mu, mu, 4.0f)) - mu;  // 2 theta
-        const float theta = 0.5f * den;
-        const float inv_theta = 2.0f / den;
-        float zval = 0.0f;
-        int32_t att = -1;
-        bool done = !active;
-        for (uint32_t round = 0; __ballot(!done) != 0ull; ++round) {
-            if (!done) {
-                const Words4 w = draw_words(a.seed, grow, ksweep, kTagZ, round, a.chain);
-                float t0, t1;
-                bool a0, a1;
-                tn_candidate(mu, gauss, theta, inv_theta, u01f(w.w0), u01f(w.w1), t0, a0);
-                tn_candidate(mu, gauss, theta, inv_theta, u01f(w.w2), u01f(w.w3), t1, a1);
-                if (a0) {
-                    zval = ys * t0;
-                    att = (int32_t)(2 * round);
-                    done = true;
-                } else if (a1) {
-                    zval = ys * t1;
-                    att = (int32_t)(2 * round + 1);
-                    done = true;
-                } else if (round + 1 >= kMaxRounds) {
-                    zval = __builtin_nanf("");
-                    done = true;
-                    capped = true;
-                }
-            }
-        }
-        if (active && (!WIDE || wave == 0)) {
-            maxatt = max(maxatt, (uint32_t)(att + 1));
-            if (a.zdbg) {
-                a.zdbg[grow] = zval;
-                a.adbg[grow] = att | (gauss ? (1 << 30) : 0);
-            }
-        }
-
-        // b += x_r^T z_r for the tile: R-term float sums, then float64
-        float zr[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            zr[r] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zval), r));
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc)
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                float acc = 0.0f;
-#pragma unroll
-                for (int r = 0; r < R; ++r) acc = fmaf(zr[r], xelem<XT>(xr[r][kc], e), acc);
-                bacc[kc][e] += on_grid((double)acc);
-            }
+        z_tile<XT, KC, R, WIDE>(a, t, ksweep, bl, bacc, maxatt, capped, parity, eta_lds);
     };
 
     // A share of the tiles is dealt out statically, interleaved over all
@@ -364,6 +383,157 @@ __device__ __forceinline__ void zpass_role(Args& a, uint32_t zrank, uint32_t nz,
                 __hip_atomic_store(&a.ctrl->z_next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
+    }
+}
+
+
+// A queue worker leaves chain a: the float64 sums of x_ij z_i over the units
+// it finished there (each wave's, added in wave order) go into the chain's b
+// accumulator, then its proposal statistics; once those additions are
+// complete, the unit count goes into the chain's z_count.
+template <int XT, int KC>
+__device__ __forceinline__ void zq_flush(Args& a, double (&bacc)[KC][XTraits<XT>::VEC], uint32_t& maxatt,
+                                         bool& capped, uint32_t units, double* red) {
+    constexpr int VEC = XTraits<XT>::VEC;
+    constexpr int CW = kWave * VEC;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const uint32_t ld = a.x.ld;
+    for (uint32_t seg = 0; seg < ld; seg += kRedCols) {
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const uint32_t col = kc * CW + lane * VEC + e;
+                if (col >= seg && col < seg + kRedCols && col < ld) red[wave * kRedCols + (col - seg)] = bacc[kc][e];
+            }
+        __syncthreads();
+        for (uint32_t c = threadIdx.x; c < kRedCols && seg + c < ld; c += kThreads) {
+            double v = red[c];
+#pragma unroll
+            for (int w = 1; w < kWPB; ++w) v += red[w * kRedCols + c];
+            __hip_atomic_fetch_add(&a.bsum[seg + c], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) bacc[kc][e] = 0.0;
+    uint32_t m = maxatt;
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    const bool anycap = __ballot(capped) != 0ull;
+    if (lane == 0) {
+        if (m) atomicMax(&a.ctrl->max_attempts, m);
+        if (anycap) atomicOr(&a.ctrl->err, kErrTnCap);
+    }
+    maxatt = 0;
+    capped = false;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(&a.ctrl->z_count, (unsigned long long)units);
+}
+
+// A worker block of a pack's shared z queue (rows of one wave each): the
+// units of its home chain, then of whichever chain has most units left, until
+// none are left anywhere.  Thread 0 reserves the next unit of the current
+// chain before the block works on the present one.  Workers never wait on
+// other blocks; the last one to finish clears the queue's counters for the
+// next launch.
+template <int XT, int KC, int R>
+__device__ __forceinline__ void zqueue_role(const SweepArgs* const* tab, uint32_t home, double* red) {
+    constexpr int VEC = XTraits<XT>::VEC;
+    constexpr int CW = kWave * VEC;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    HSP_GLOBAL PackQ* q = ((Args*)tab[home])->zq;
+    const uint32_t n = q->nchains;
+    float bl[KC][VEC];
+    double bacc[KC][VEC];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) bacc[kc][e] = 0.0;
+    uint32_t maxatt = 0, parity = 0;
+    bool capped = false;
+
+    uint32_t c = home;
+    if (threadIdx.x == 0) red[0] = (double)atomicAdd(&q->next[c], 1u);
+    __syncthreads();
+    uint32_t u = (uint32_t)red[0];
+    __syncthreads();
+    for (;;) {
+        const uint32_t nunits = q->units[c];
+        if (u < nunits) {
+            Args& a = *(Args*)tab[c];
+            const uint32_t ksweep = a.ctrl->sweep + 1u;
+            const uint32_t ld = a.x.ld, U = a.z_unit, n_tiles = (a.x.N + R - 1) / R;
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const uint32_t col = kc * CW + lane * VEC + e;
+                    bl[kc][e] = col < ld ? a.beta32[col] : 0.0f;
+                }
+            uint32_t finished = 0;
+            while (u < nunits) {
+                uint32_t nxt = 0;
+                if (threadIdx.x == 0) nxt = atomicAdd(&q->next[c], 1u);
+                for (uint32_t j = (uint32_t)wave; j < U; j += kWPB) {
+                    const uint32_t t = u * U + j;
+                    if (t < n_tiles) z_tile<XT, KC, R, false>(a, t, ksweep, bl, bacc, maxatt, capped, parity, nullptr);
+                }
+                ++finished;
+                if (threadIdx.x == 0) red[0] = (double)nxt;
+                __syncthreads();
+                u = (uint32_t)red[0];
+                __syncthreads();
+            }
+            zq_flush<XT, KC>(a, bacc, maxatt, capped, finished, red);
+        }
+        // the chain with most units left, the first of equals; a claim that
+        // comes too late only sends the block back here
+        if (wave == 0) {
+            unsigned long long key = 0ull;
+            for (uint32_t j = (uint32_t)lane; j < n; j += kWave) {
+                const uint32_t nx = __hip_atomic_load(&q->next[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t un = q->units[j];
+                const unsigned long long k =
+                    un > nx ? ((unsigned long long)(un - nx) << 32) | (0xFFFFFFFFu - j) : 0ull;
+                key = k > key ? k : key;
+            }
+#pragma unroll
+            for (int off = kWave / 2; off >= 1; off >>= 1) {
+                const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(key >> 32), off);
+                const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)key, off);
+                const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+                key = o > key ? o : key;
+            }
+            if (lane == 0) {
+                if (key == 0ull) {
+                    red[0] = -1.0;
+                } else {
+                    const uint32_t cc = 0xFFFFFFFFu - (uint32_t)key;
+                    red[0] = (double)cc;
+                    red[1] = (double)atomicAdd(&q->next[cc], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        const double r0 = red[0], r1 = red[1];
+        __syncthreads();
+        if (r0 < 0.0) break;
+        c = (uint32_t)r0;
+        u = (uint32_t)r1;
+    }
+    if (threadIdx.x == 0) red[0] = atomicAdd(&q->done, 1u) == q->workers - 1 ? 1.0 : 0.0;
+    __syncthreads();
+    if (red[0] != 0.0) {
+        // every worker has made its last claim
+        for (uint32_t j = threadIdx.x; j < n; j += kThreads)
+            __hip_atomic_store(&q->next[j], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) __hip_atomic_store(&q->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

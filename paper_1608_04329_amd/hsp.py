@@ -30,7 +30,8 @@ EXPORTS = ["hsp_default_options", "hsp_max_p", "hsp_gram", "hsp_gram_noalloc", "
            "hsp_tile_schedule", "hsp_read_ceiling", "hsp_batch_create", "hsp_batch_size",
            "hsp_batch_chain", "hsp_batch_sweep", "hsp_batch_sync", "hsp_batch_set_timing",
            "hsp_batch_get_timing", "hsp_batch_last_error", "hsp_batch_destroy", "hsp_get_plan",
-           "hsp_sort_rows", "hsp_batch_get_plan", "hsp_tune_key", "hsp_tune_cache_put", "hsp_tune_cache_get"]
+           "hsp_sort_rows", "hsp_batch_get_plan", "hsp_tune_key", "hsp_tune_cache_put", "hsp_tune_cache_get",
+           "hsp_batch_set_zqueue"]
 
 
 class hsp_options(C.Structure):
@@ -113,6 +114,7 @@ def load():
     L.hsp_sort_rows.argtypes = [vp]; L.hsp_sort_rows.restype = st
     L.hsp_batch_get_plan.argtypes = [vp, pi64, pi64, pi64, C.c_char_p, i64]
     L.hsp_batch_get_plan.restype = st
+    L.hsp_batch_set_zqueue.argtypes = [vp, C.c_int32]; L.hsp_batch_set_zqueue.restype = st
     L.hsp_tune_key.argtypes = [vp, C.c_char_p, i64]; L.hsp_tune_key.restype = st
     L.hsp_tune_cache_put.argtypes = [C.c_char_p, C.c_char_p, C.c_char_p]; L.hsp_tune_cache_put.restype = st
     L.hsp_tune_cache_get.argtypes = [C.c_char_p, C.c_char_p, C.c_char_p, i64]
@@ -340,6 +342,10 @@ def hsp_batch_get_plan(b):
     return tuple(x.value for x in v) + (note.value.decode(),)
 
 
+def hsp_batch_set_zqueue(b, kib):
+    _bcheck(load().hsp_batch_set_zqueue(b, int(kib)), b)
+
+
 def hsp_tune_key(h):
     buf = C.create_string_buffer(512)
     _check(load().hsp_tune_key(h, buf, 512), h)
@@ -545,6 +551,10 @@ class Batch:
 
     def plan(self):
         return hsp_batch_get_plan(self.b)
+
+    def set_zqueue(self, kib):
+        """Shared z queue per pack in units of about kib KiB of X (0: off)."""
+        hsp_batch_set_zqueue(self.b, kib)
 
     def close(self):
         if self.b:
