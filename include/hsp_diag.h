@@ -80,14 +80,17 @@ hsp_status hsp_get_plan(hsp_state* s, int64_t* group_blocks, int64_t* z_blocks, 
 hsp_status hsp_batch_get_plan(hsp_batch* b, int64_t* mc_blocks, int64_t* bw_pct, int64_t* packs, char* note,
                               int64_t note_cap);
 
-/* How the batch's packs of chains with short rows (each row within one
- * wave) take their z passes: kib > 0, from one shared queue per pack, in
- * units of about kib KiB of X (the default is 64); kib = 0, each chain with
- * z-pass blocks of its own.  The packs are planned again at the next
- * hsp_batch_sweep and the autotuner is switched off for the batch.  Either
- * way every chain draws bitwise what it draws alone.  HSP_EINVAL unless
- * 0 <= kib <= 4096. */
-hsp_status hsp_batch_set_zqueue(hsp_batch* b, int32_t kib);
+/* Two launch-shape choices of a batch (defaults 64 and 16), each leaving
+ * every chain's draws bitwise those of the chain alone:
+ *  - zq_kib: packs of chains with short rows (each row within one wave)
+ *    take their z passes from one shared queue per pack, in units of about
+ *    zq_kib KiB of X; 0 gives each chain z-pass blocks of its own;
+ *  - pre_blocks: chains served by a multi-chain z pass (p > 16) draw lambda,
+ *    tau, nu, xi and factor Q in a launch beside that pass, with this many
+ *    blocks per chain; 0 does all of their p-side after the pass.
+ * The packs are planned again at the next hsp_batch_sweep and the autotuner
+ * is switched off for the batch.  HSP_EINVAL unless both lie in [0, 4096]. */
+hsp_status hsp_batch_set_shape(hsp_batch* b, int32_t zq_kib, int32_t pre_blocks);
 
 /* The autotuner's cache key of a state (its device, shape and plan format). */
 hsp_status hsp_tune_key(hsp_state* s, char* key, int64_t cap);

@@ -972,7 +972,7 @@ struct Pack {
     // launch, mc_gz blocks) precedes the launch of their p-side groups
     bool mc = false;
     McArgs* dmc = nullptr;          // device copy of the pass's description
-    double* mc_partial = nullptr;   // mc_gz x kMcChains x ld
+    double* mc_partial = nullptr;   // mc_gz x kMcChains x mc_stride(ld)
     uint32_t* mc_count = nullptr;   // group and unit counters
     uint32_t mc_gz = 0, mc_ld = 0;
     std::vector<size_t> chains;             // indices into hsp_batch::chains
@@ -985,6 +985,10 @@ struct Pack {
     // blocks after every p-side group take all their z passes
     bool queue = false;
     uint32_t workers = 0;
+    // p-side groups split over two launches (tile path only): a `pre` pack
+    // draws lambda, tau, nu, xi and factors Q while the multi-chain pass runs;
+    // the multi-chain pack after it (`split`) takes b and draws beta
+    bool pre = false, split = false;
     std::vector<uint32_t> home;             // home chain of each worker (pack-local index)
     std::vector<uint32_t> unit_tiles;       // row tiles per unit of each chain
     PackQ* dq = nullptr;                    // the queue's counters (device)
@@ -1006,8 +1010,9 @@ struct hsp_batch {
     uint32_t zq_kib = 64;      // packs of row-per-wave chains share one z queue, units of about this
                                // many KiB of X (0: every chain has z blocks of its own)
     bool overlap = true;       // multi-chain passes on a second stream, beside the other packs
-    hipStream_t side = nullptr;  // that stream (captured into the graph only)
-    hipEvent_t fork = nullptr, join = nullptr;
+    uint32_t pre_gp = 0;       // blocks per chain factoring Q beside the multi-chain pass (0: after it)
+    hipStream_t side = nullptr, side2 = nullptr;  // streams of the passes and of the pre packs
+    hipEvent_t fork = nullptr, join = nullptr, join2 = nullptr;  // (captured into the graph only)
     bool autotune = false;
     std::string plan_note = "built-in";
 };
@@ -1038,7 +1043,9 @@ void free_batch(hsp_batch* b) {
     free_packs(b);
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->join) (void)hipEventDestroy(b->join);
+    if (b->join2) (void)hipEventDestroy(b->join2);
     if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->side2) (void)hipStreamDestroy(b->side2);
     b->timer.reset();
     for (auto it = b->chains.rbegin(); it != b->chains.rend(); ++it) free_state(*it);  // borrowers first
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -1174,6 +1181,21 @@ hsp_status plan_packs(hsp_batch* b) {
                 pk.gp.assign(pk.chains.size(), each);
                 pk.gz.assign(pk.chains.size(), 0);
                 pk.blocks = each * (uint32_t)pk.chains.size();
+                if (b->pre_gp && nt) {
+                    // the factorisations go beside the pass, in a launch of their own
+                    Pack pre;
+                    pre.xtype = HSP_X_BF16;
+                    pre.chunks = pk.chunks;
+                    pre.pre = true;
+                    pre.chains = pk.chains;
+                    const uint32_t g = std::max<uint32_t>(
+                        1, std::min<uint32_t>({gmax, b->pre_gp, (uint32_t)cap / 2 / (uint32_t)pk.chains.size()}));
+                    pre.gp.assign(pk.chains.size(), g);
+                    pre.gz.assign(pk.chains.size(), 0);
+                    pre.blocks = g * (uint32_t)pk.chains.size();
+                    pk.split = true;
+                    b->packs.push_back(std::move(pre));
+                }
                 b->packs.push_back(std::move(pk));
             }
         }
@@ -1283,8 +1305,13 @@ hsp_status plan_packs(hsp_batch* b) {
         uint32_t blk = 0;
         for (size_t j = 0; j < nc; ++j) {
             hsp_state* s = b->chains[pk.chains[j]];
-            // a chain of a multi-chain pack takes b from the pass before
-            SweepArgs h = sweep_args(s, pk.mc ? (kModeSweep & ~kModeZ) | kModeBsum : kModeSweep);
+            // a chain of a multi-chain pack takes b from the pass before; a
+            // pre pack's launch stops where b is needed, and the split pack's
+            // launch starts there
+            uint32_t mode = pk.mc ? (kModeSweep & ~kModeZ) | kModeBsum : kModeSweep;
+            if (pk.pre) mode = kModeLambda | kModeTau | kModeNuXi | kModeBeta | kModePre;
+            else if (pk.split) mode = kModeBeta | kModeRecord | kModeAdvance | kModeBsum | kModePost;
+            SweepArgs h = sweep_args(s, mode);
             h.gp = pk.gp[j];
             h.gz = pk.gz[j];
             h.z_static_pct = kZStaticPctDefault;
@@ -1299,7 +1326,7 @@ hsp_status plan_packs(hsp_batch* b) {
                 h.zq = dev_ptr(pk.dq);
             }
             h.block0 = blk;
-            if (s->x.p > (uint32_t)kSmallP) {
+            if (s->x.p > (uint32_t)kSmallP && !pk.split) {
                 const uint32_t nt = (s->x.p + kTile - 1) / kTile;
                 std::vector<uint32_t> tasks, off;
                 chol_schedule(nt, h.gp, &tasks, &off);
@@ -1340,7 +1367,8 @@ hsp_status plan_packs(hsp_batch* b) {
             m.gz = pk.mc_gz;
             m.zgroups = (m.gz + kZGroup - 1) / kZGroup;
             const size_t ncount = (size_t)m.zgroups + 64;
-            if (dalloc(&pk.dmc, 1) || dalloc(&pk.mc_partial, (size_t)m.gz * kMcChains * pk.mc_ld) ||
+            m.pstride = mc_stride(pk.mc_ld);
+            if (dalloc(&pk.dmc, 1) || dalloc(&pk.mc_partial, (size_t)m.gz * kMcChains * m.pstride) ||
                 dalloc(&pk.mc_count, ncount))
                 return batch_fail(b, HSP_ENOMEM, "pack allocation failed");
             m.partial = dev_ptr(pk.mc_partial);
@@ -1360,9 +1388,9 @@ hsp_status batch_build(hsp_batch* b) {
         if (st != HSP_OK) return st;
     }
     if (b->graph) return HSP_OK;
-    bool any_mc = false, any_plain = false;
-    for (const Pack& pk : b->packs) (pk.mc ? any_mc : any_plain) = true;
-    const bool overlap = b->overlap && any_mc && any_plain;
+    bool any_mc = false, any_plain = false, any_pre = false;
+    for (const Pack& pk : b->packs) (pk.pre ? any_pre : pk.mc ? any_mc : any_plain) = true;
+    const bool overlap = b->overlap && any_mc && (any_plain || any_pre);
     hipError_t e = hipSuccess;
     if (overlap && !b->side) {
         e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
@@ -1370,32 +1398,45 @@ hsp_status batch_build(hsp_batch* b) {
         if (!e) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
         if (e) return batch_fail(b, HSP_EHIP, std::string("batch side stream: ") + hipGetErrorString(e));
     }
+    if (overlap && any_pre && !b->side2) {
+        e = hipStreamCreateWithFlags(&b->side2, hipStreamNonBlocking);
+        if (!e) e = hipEventCreateWithFlags(&b->join2, hipEventDisableTiming);
+        if (e) return batch_fail(b, HSP_EHIP, std::string("batch side stream: ") + hipGetErrorString(e));
+    }
     hipGraph_t g = nullptr;
     e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    auto launch = [&](const Pack& pk, hipStream_t st) {
+        return pack_launch(pk.xtype, pk.chunks, pk.dtab, pk.dmap, pk.blocks, st);
+    };
     if (overlap) {
-        // The multi-chain passes wait on nothing, so they may run beside the
-        // other packs (whose blocks then become resident as they finish); the
-        // launches that wait inside (the packs, and the p-side launch of the
-        // multi-chain chains) stay one after another on the batch's stream.
+        // The multi-chain passes, and the pre packs (whose blocks wait only
+        // on blocks of their own launch), may run beside the other packs, on
+        // streams of their own; blocks of one launch become resident as
+        // blocks of another finish.  The launches that take b from a pass
+        // follow them on the batch's stream.
         if (!e) e = hipEventRecord(b->fork, b->stream);
         if (!e) e = hipStreamWaitEvent(b->side, b->fork, 0);
         for (size_t i = 0; !e && i < b->packs.size(); ++i)
             if (b->packs[i].mc) e = mc_launch(b->packs[i].dmc, b->packs[i].mc_ld, b->packs[i].mc_gz, b->side);
         if (!e) e = hipEventRecord(b->join, b->side);
-        for (size_t i = 0; !e && i < b->packs.size(); ++i) {
-            const Pack& pk = b->packs[i];
-            if (!pk.mc) e = pack_launch(pk.xtype, pk.chunks, pk.dtab, pk.dmap, pk.blocks, b->stream);
+        if (any_pre) {
+            if (!e) e = hipStreamWaitEvent(b->side2, b->fork, 0);
+            for (size_t i = 0; !e && i < b->packs.size(); ++i)
+                if (b->packs[i].pre) e = launch(b->packs[i], b->side2);
+            if (!e) e = hipEventRecord(b->join2, b->side2);
         }
+        for (size_t i = 0; !e && i < b->packs.size(); ++i)
+            if (!b->packs[i].mc && !b->packs[i].pre) e = launch(b->packs[i], b->stream);
         if (!e) e = hipStreamWaitEvent(b->stream, b->join, 0);
-        for (size_t i = 0; !e && i < b->packs.size(); ++i) {
-            const Pack& pk = b->packs[i];
-            if (pk.mc) e = pack_launch(pk.xtype, pk.chunks, pk.dtab, pk.dmap, pk.blocks, b->stream);
-        }
+        if (!e && any_pre) e = hipStreamWaitEvent(b->stream, b->join2, 0);
+        for (size_t i = 0; !e && i < b->packs.size(); ++i)
+            if (b->packs[i].mc) e = launch(b->packs[i], b->stream);
     } else {
+        // in pack order: a pre pack comes just before its multi-chain pack
         for (size_t i = 0; !e && i < b->packs.size(); ++i) {
             const Pack& pk = b->packs[i];
             if (pk.mc) e = mc_launch(pk.dmc, pk.mc_ld, pk.mc_gz, b->stream);
-            if (!e) e = pack_launch(pk.xtype, pk.chunks, pk.dtab, pk.dmap, pk.blocks, b->stream);
+            if (!e) e = launch(pk, b->stream);
         }
     }
     hipError_t e2 = hipStreamEndCapture(b->stream, &g);
@@ -1429,7 +1470,7 @@ std::string batch_tune_key(const hsp_batch* b) {
     char hex[17];
     std::snprintf(hex, sizeof hex, "%016llx", (unsigned long long)h);
     const hsp_state* s0 = b->chains[0];
-    return "batch-v4 " + device_tag(s0->device, s0->num_cus) + " chains=" + std::to_string(b->chains.size()) +
+    return "batch-v5 " + device_tag(s0->device, s0->num_cus) + " chains=" + std::to_string(b->chains.size()) +
            " h=" + hex;
 }
 
@@ -1458,26 +1499,29 @@ hsp_status time_batch(hsp_batch* b, int warm, int timed, double* ms) {
 
 // The autotuner for a batch: blocks of each multi-chain z pass, chains per
 // pack, the bandwidth the pack split model gives a z-pass block, whether the
-// packs share one z queue (and its unit size) and whether the multi-chain
-// passes run beside the other packs, by timing a few batched sweeps of every
-// candidate (or from the cache).  Every chain's state is put back afterwards.
+// packs share one z queue (and its unit size), how many blocks per chain
+// factor Q beside the multi-chain pass, and whether the passes run beside
+// the other packs, by timing a few batched sweeps of every candidate (or
+// from the cache).  Every chain's state is put back afterwards.
 hsp_status batch_tune(hsp_batch* b) {
     const std::string key = batch_tune_key(b);
     const char* path = tune_cache_path();
     std::string cached;
-    long mcg = 0, bwp = 0, pmax = 0, ov = 1, zq = 0;
+    long mcg = 0, bwp = 0, pmax = 0, ov = 1, zq = 0, pre = 0;
     if (path && tune_cache_get(path, key, &cached) && tune_parse(cached, "mc_gz", &mcg) &&
         tune_parse(cached, "bw", &bwp) && tune_parse(cached, "pack", &pmax) && tune_parse(cached, "ov", &ov) &&
-        tune_parse(cached, "zq", &zq) && mcg >= 0 && mcg <= 65536 && bwp >= 10 && bwp <= 1000 && pmax >= 0 &&
-        pmax <= 65536 && (ov == 0 || ov == 1) && zq >= 0 && zq <= 4096) {
+        tune_parse(cached, "zq", &zq) && tune_parse(cached, "pre", &pre) && mcg >= 0 && mcg <= 65536 &&
+        bwp >= 10 && bwp <= 1000 && pmax >= 0 && pmax <= 65536 && (ov == 0 || ov == 1) && zq >= 0 &&
+        zq <= 4096 && pre >= 0 && pre <= 4096) {
         b->mc_gz = (uint32_t)mcg;
         b->bw_pct = (uint32_t)bwp;
         b->pack_max = (uint32_t)pmax;
         b->overlap = ov != 0;
         b->zq_kib = (uint32_t)zq;
+        b->pre_gp = (uint32_t)pre;
         b->plan_note = "mc_gz=" + std::to_string(mcg) + " bw=" + std::to_string(bwp) + " pack=" +
                        std::to_string(pmax) + " ov=" + std::to_string(ov) + " zq=" + std::to_string(zq) +
-                       " (cache)";
+                       " pre=" + std::to_string(pre) + " (cache)";
         return HSP_OK;
     }
     std::vector<SavedChain> saved(b->chains.size());
@@ -1543,6 +1587,25 @@ hsp_status batch_tune(hsp_batch* b) {
     b->bw_pct = best_bw;
     b->pack_max = best_pm;
     b->zq_kib = best_zq;
+    uint32_t best_pre = b->pre_gp;
+    if (units) {
+        // blocks per chain factoring Q beside the multi-chain pass (0: after it)
+        const uint32_t tried = b->pre_gp;
+        for (uint32_t pg : {0u, 8u, 32u}) {
+            if (pg == tried) continue;
+            b->pre_gp = pg;
+            st = batch_build(b);
+            double ms = 0.0;
+            if (!st) st = time_batch(b, 1, 3, &ms);
+            free_packs(b);
+            if (st) return st;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_pre = pg;
+            }
+        }
+        b->pre_gp = best_pre;
+    }
     bool best_ov = true;
     {
         // the passes beside the packs, or all launches one after another
@@ -1562,9 +1625,9 @@ hsp_status batch_tune(hsp_batch* b) {
         st = restore_chain(b->chains[i], saved[i]);
         if (st) return batch_fail(b, st, b->chains[i]->err);
     }
-    char buf[128];
-    std::snprintf(buf, sizeof buf, "mc_gz=%u bw=%u pack=%u ov=%d zq=%u ms=%.4f", best_mc, best_bw, best_pm,
-                  (int)best_ov, best_zq, best_ms);
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "mc_gz=%u bw=%u pack=%u ov=%d zq=%u pre=%u ms=%.4f", best_mc, best_bw, best_pm,
+                  (int)best_ov, best_zq, best_pre, best_ms);
     b->plan_note = std::string(buf) + " (measured)";
     if (path) (void)tune_cache_put(path, key, buf);
     return HSP_OK;
@@ -2089,13 +2152,15 @@ hsp_status hsp_batch_get_plan(hsp_batch* b, int64_t* mc_blocks, int64_t* bw_pct,
     return HSP_OK;
 }
 
-hsp_status hsp_batch_set_zqueue(hsp_batch* b, int32_t kib) {
+hsp_status hsp_batch_set_shape(hsp_batch* b, int32_t zq_kib, int32_t pre_blocks) {
     if (!b) return HSP_EINVAL;
-    if (kib < 0 || kib > 4096) return batch_fail(b, HSP_EINVAL, "kib must lie in [0, 4096]");
+    if (zq_kib < 0 || zq_kib > 4096) return batch_fail(b, HSP_EINVAL, "zq_kib must lie in [0, 4096]");
+    if (pre_blocks < 0 || pre_blocks > 4096) return batch_fail(b, HSP_EINVAL, "pre_blocks must lie in [0, 4096]");
     free_packs(b);  // planned again at the next sweep
-    b->zq_kib = (uint32_t)kib;
+    b->zq_kib = (uint32_t)zq_kib;
+    b->pre_gp = (uint32_t)pre_blocks;
     b->autotune = false;
-    b->plan_note = "zq=" + std::to_string(kib) + " (set)";
+    b->plan_note = "zq=" + std::to_string(zq_kib) + " pre=" + std::to_string(pre_blocks) + " (set)";
     return HSP_OK;
 }
 

@@ -107,6 +107,9 @@ enum : uint32_t {
     kModeRecord = 32u,   // write the draw of this sweep into the ring
     kModeAdvance = 64u,  // count the sweep as completed
     kModeBsum = 128u,    // b = X^T z from bsum, accumulated by an earlier launch (no z pass here)
+    // the tile path's p-side in two launches of one sweep (p > 16 only):
+    kModePre = 256u,     // lambda, tau, nu, xi, the noise of beta and the factorisation, then stop
+    kModePost = 512u,    // only what needs b: beta from the factorisation of the earlier launch
 };
 
 // Layout of X in device memory: row-major, leading dimension ld elements,
@@ -208,6 +211,10 @@ constexpr int kMcKs = 8;
 constexpr int kMcRows = 16;
 constexpr int kMcUnit = 64;  // tiles per claimed unit; each unit's X^T z is rounded to the grid
 constexpr uint32_t kMcMaxLd = 4u * 32u * kMcKs;
+// 32-column steps per wave of the pass for rows of ld elements, and the
+// columns its four waves cover
+inline uint32_t mc_steps(uint32_t ld) { return ld <= 4u * 32u * 4u ? 4u : (uint32_t)kMcKs; }
+inline uint32_t mc_stride(uint32_t ld) { return 4u * 32u * mc_steps(ld); }
 
 struct McArgs {
     XLayout x;                          // the shared design (bfloat16)
@@ -215,7 +222,8 @@ struct McArgs {
     uint32_t nchains;                   // chains served (<= kMcChains)
     uint32_t gz;                        // blocks of the launch
     uint32_t zgroups;                   // ceil(gz / kZGroup)
-    HSP_GLOBAL double* partial;         // gz x kMcChains x ld float64 block partials of X^T z
+    HSP_GLOBAL double* partial;         // gz x kMcChains x pstride float64 block partials of X^T z
+    uint32_t pstride;                   // mc_stride(ld): every column a block's waves cover
     HSP_GLOBAL uint32_t* count;         // [0, zgroups): group arrivals; [zgroups]: groups done;
                                         // [zgroups + 32]: next unit (zero between launches)
     HSP_GLOBAL const SweepArgs* chain[kMcChains];  // the chains' launch descriptions

@@ -182,21 +182,31 @@ __device__ void mc_role(McView& m, uint32_t rank, double* lds) {
         for (int h = 0; h < 2; ++h) db[s][h] = F32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
     // a unit's X^T z into the block's float64 partial: D entry r of step
-    // (s, h) is column 32 (ks0 + s) + 16 h + 4 q + r of chain n
+    // (s, h) is column 32 (ks0 + s) + 16 h + 4 q + r of chain n.  Every lane
+    // stores all of its entries (rows of the partial span every column the
+    // waves cover, and D is zero past ld and for chains past C), with no
+    // branch between the stores, so they are all in flight together; the
+    // earlier sums are loaded four steps at a time, likewise.
     auto flush = [&]() {
-        if (live) {
-            HSP_GLOBAL double* dst = m.partial + ((size_t)rank * kMcChains + n) * ld;
+        HSP_GLOBAL double* dst = m.partial + ((size_t)rank * kMcChains + n) * m.pstride;
 #pragma unroll
-            for (int s = 0; s < KS; ++s)
+        for (int s0 = 0; s0 < KS; s0 += 4) {
+            double old[4][2][4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        old[s][h][r] = wrote ? ldc(dst + 32u * (ks0 + s0 + s) + 16u * h + 4u * q + r) : 0.0;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const uint32_t col = 32u * (ks0 + s) + 16u * h + 4u * q + r;
-                        if (col < ld) {
-                            const double v = on_grid((double)db[s][h][r]);
-                            stc(dst + col, wrote ? ldc(dst + col) + v : v);
-                        }
+                        const double v = on_grid((double)db[s0 + s][h][r]);
+                        stc(dst + 32u * (ks0 + s0 + s) + 16u * h + 4u * q + r, wrote ? old[s][h][r] + v : v);
                     }
         }
         wrote = true;
@@ -341,7 +351,7 @@ __device__ void mc_role(McView& m, uint32_t rank, double* lds) {
     for (uint32_t e = threadIdx.x; e < C * ld; e += kThreads) {
         const uint32_t c = e / ld, col = e % ld;
         double v = 0.0;
-        for (uint32_t r = 0; r < gsize; ++r) v += ldc(&m.partial[((size_t)(g0 + r) * kMcChains + c) * ld + col]);
+        for (uint32_t r = 0; r < gsize; ++r) v += ldc(&m.partial[((size_t)(g0 + r) * kMcChains + c) * m.pstride + col]);
         Args& a = *(Args*)m.chain[c];
         __hip_atomic_fetch_add(&a.bsum[col], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }

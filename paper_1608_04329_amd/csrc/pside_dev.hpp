@@ -869,26 +869,32 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
     Tile& S = *reinterpret_cast<Tile*>(lds);
     Tile& T = *reinterpret_cast<Tile*>(lds + kTile * kTileLd);
     double* flag = lds + 2 * kTile * kTileLd - 1;  // T's unused padding corner
-    const double tau = hyper_lambda_tau(a, k, rank == 0, lds);
-    group_sync(g);  // lambda^-2 and the new tau^-2 in memory
     double* s_noise = a.vec + p;
-    if (rank == g.size - 1) {
-        if (a.mode & kModeNuXi) hyper_nu_xi(a, k);
-        if (a.mode & kModeBeta)
-            for (uint32_t i = threadIdx.x; i < p; i += kThreads) {
-                const Words4 w = draw_words(a.seed, i, k, kTagBetaS, 0, a.chain);
-                stc(&s_noise[i], box_muller_d(u01d(w.w0), u01d(w.w1)));
-            }
-    }
-
     bool ok = true;
-    if (a.mode & kModeBeta) {
-        // Factorisation of [Q | I]: U in A (upper), L^-1 = U^-T in Linv (lower),
-        // as this block's list of tile tasks.
-        ok = run_tasks(a, g, rank, tau, S, T, flag);
-        group_sync(g);
-        ok = ok && !group_failed(g, flag);
+    if (!(a.mode & kModePost)) {
+        const double tau = hyper_lambda_tau(a, k, rank == 0, lds);
+        group_sync(g);  // lambda^-2 and the new tau^-2 in memory
+        if (rank == g.size - 1) {
+            if (a.mode & kModeNuXi) hyper_nu_xi(a, k);
+            if (a.mode & kModeBeta)
+                for (uint32_t i = threadIdx.x; i < p; i += kThreads) {
+                    const Words4 w = draw_words(a.seed, i, k, kTagBetaS, 0, a.chain);
+                    stc(&s_noise[i], box_muller_d(u01d(w.w0), u01d(w.w1)));
+                }
+        }
+        if (a.mode & kModeBeta) {
+            // Factorisation of [Q | I]: U in A (upper), L^-1 = U^-T in Linv
+            // (lower), as this block's list of tile tasks.
+            ok = run_tasks(a, g, rank, tau, S, T, flag);
+            group_sync(g);
+            ok = ok && !group_failed(g, flag);
+        }
+    } else {
+        // an earlier launch of this sweep drew lambda, tau, nu, xi and the
+        // noise of beta and factored Q; its failure flags are in memory
+        ok = !group_failed(g, flag);
     }
+    if (a.mode & kModePre) return;  // b is taken by a later launch of this sweep
 
     if (a.mode & kModeZ) {
         if (threadIdx.x == 0) {
@@ -1027,8 +1033,13 @@ __device__ __forceinline__ void pside_role(Args& a, uint32_t rank, uint32_t k, d
     g.slot = 0;
     g.npotrf = 0;
     g.timeout = a.timeout_ticks;
-    if (a.x.p <= (uint32_t)kSmallP) small_path(a, g, k, lds);
-    else tile_path(a, g, rank, k, lds);
+    // the two-launch split is for the tile path; a launch never asks the
+    // one-block path for half a sweep
+    if (a.x.p <= (uint32_t)kSmallP) {
+        if (!(a.mode & (kModePre | kModePost))) small_path(a, g, k, lds);
+    } else {
+        tile_path(a, g, rank, k, lds);
+    }
     // the last barrier above was passed by every block of the group, and the
     // z-pass blocks have all finished if they ran: close the launch
     if (rank == 0) {
@@ -1039,7 +1050,7 @@ __device__ __forceinline__ void pside_role(Args& a, uint32_t rank, uint32_t k, d
             if (a.mode & kModeTau) *a.tau_m2 = current_tau(a);
             if (a.mode & kModeAdvance) a.ctrl->sweep = k;
         }
-        if (a.x.p > (uint32_t)kSmallP && (a.mode & kModeBeta)) {
+        if (a.x.p > (uint32_t)kSmallP && (a.mode & kModeBeta) && !(a.mode & kModePost)) {
             const uint32_t nt = padded(a.x.p) / kTile;
             for (uint32_t e = threadIdx.x; e < 2 * nt * nt; e += kThreads) a.ver[e] = 0u;
             if (threadIdx.x == 0) a.ctrl->task_next = 0u;

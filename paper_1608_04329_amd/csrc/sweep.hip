@@ -164,8 +164,8 @@ int pack_capacity(int xtype, int chunks, int num_cus) {
 hipError_t mc_launch(const McArgs* mc, uint32_t ld, uint32_t gz, hipStream_t st) {
     if (ld > kMcMaxLd) return hipErrorInvalidValue;
     void* args[] = {&mc};
-    const void* f = ld <= 4u * 32u * 4u ? reinterpret_cast<const void*>(&mc_zpass_kernel<4>)
-                                        : reinterpret_cast<const void*>(&mc_zpass_kernel<kMcKs>);
+    const void* f = mc_steps(ld) == 4u ? reinterpret_cast<const void*>(&mc_zpass_kernel<4>)
+                                       : reinterpret_cast<const void*>(&mc_zpass_kernel<kMcKs>);
     return hipLaunchKernel(f, dim3(gz), dim3(kThreads), args, 0, st);
 }
 

@@ -31,7 +31,7 @@ EXPORTS = ["hsp_default_options", "hsp_max_p", "hsp_gram", "hsp_gram_noalloc", "
            "hsp_batch_chain", "hsp_batch_sweep", "hsp_batch_sync", "hsp_batch_set_timing",
            "hsp_batch_get_timing", "hsp_batch_last_error", "hsp_batch_destroy", "hsp_get_plan",
            "hsp_sort_rows", "hsp_batch_get_plan", "hsp_tune_key", "hsp_tune_cache_put", "hsp_tune_cache_get",
-           "hsp_batch_set_zqueue"]
+           "hsp_batch_set_shape"]
 
 
 class hsp_options(C.Structure):
@@ -114,7 +114,7 @@ def load():
     L.hsp_sort_rows.argtypes = [vp]; L.hsp_sort_rows.restype = st
     L.hsp_batch_get_plan.argtypes = [vp, pi64, pi64, pi64, C.c_char_p, i64]
     L.hsp_batch_get_plan.restype = st
-    L.hsp_batch_set_zqueue.argtypes = [vp, C.c_int32]; L.hsp_batch_set_zqueue.restype = st
+    L.hsp_batch_set_shape.argtypes = [vp, C.c_int32, C.c_int32]; L.hsp_batch_set_shape.restype = st
     L.hsp_tune_key.argtypes = [vp, C.c_char_p, i64]; L.hsp_tune_key.restype = st
     L.hsp_tune_cache_put.argtypes = [C.c_char_p, C.c_char_p, C.c_char_p]; L.hsp_tune_cache_put.restype = st
     L.hsp_tune_cache_get.argtypes = [C.c_char_p, C.c_char_p, C.c_char_p, i64]
@@ -342,8 +342,8 @@ def hsp_batch_get_plan(b):
     return tuple(x.value for x in v) + (note.value.decode(),)
 
 
-def hsp_batch_set_zqueue(b, kib):
-    _bcheck(load().hsp_batch_set_zqueue(b, int(kib)), b)
+def hsp_batch_set_shape(b, zq_kib, pre_blocks):
+    _bcheck(load().hsp_batch_set_shape(b, int(zq_kib), int(pre_blocks)), b)
 
 
 def hsp_tune_key(h):
@@ -552,9 +552,10 @@ class Batch:
     def plan(self):
         return hsp_batch_get_plan(self.b)
 
-    def set_zqueue(self, kib):
-        """Shared z queue per pack in units of about kib KiB of X (0: off)."""
-        hsp_batch_set_zqueue(self.b, kib)
+    def set_shape(self, zq_kib=64, pre_blocks=16):
+        """Shared z queue per pack in units of about zq_kib KiB of X (0: off);
+        blocks per chain factoring Q beside a multi-chain pass (0: after it)."""
+        hsp_batch_set_shape(self.b, zq_kib, pre_blocks)
 
     def close(self):
         if self.b:

@@ -257,3 +257,24 @@ def test_multi_chain_off_equals_lone_chains(env):
         bl, tl, _ = s.draws()
         s.close()
         assert np.array_equal(batch[i][0], bl) and np.array_equal(batch[i][1], tl)
+
+
+@pytest.mark.parametrize("pre", [0, 8, 32])
+def test_factorisation_beside_the_pass_changes_nothing(env, pre):
+    """Chains of a multi-chain pass may draw lambda, tau, nu, xi and factor Q
+    in a launch beside the pass (p > 16) and take b after it: the same
+    arithmetic as one launch after the pass, so every draw is bitwise the
+    same for any number of blocks per chain, or with no such launch."""
+    sets = [((3001, 1000, 71), "bf16", 4), ((2500, 12, 73), "bf16", 2), ((2051, 257, 62), "f32", 1),
+            ((1777, 130, 74), "bf16", 3)]
+    outs = {}
+    for blocks in (16, pre):
+        _, b = make_batch(env, sets, seed=17, chain_id=1, record_lambda=True)
+        b.set_shape(64, blocks)
+        b.sweep(3)
+        b.sync()
+        outs[blocks] = [b.chain(i).draws() for i in range(len(b))]
+        b.close()
+    for i, (x, y) in enumerate(zip(outs[16], outs[pre])):
+        assert x[3] == y[3] == 3
+        assert all(np.array_equal(u, v) for u, v in zip(x[:3], y[:3])), (i, pre)

@@ -40,8 +40,8 @@ def run_batch(env, data, kib):
     datasets = [(torch.from_numpy(d.X).cuda(), torch.from_numpy(d.y).cuda(), xt) for d, xt, _ in data]
     b = hsp.Batch(datasets, [c for _, _, c in data], seed=21, chain_id=7, record_lambda=True)
     if kib is not None:
-        b.set_zqueue(kib)
-        assert b.plan()[3] == f"zq={kib} (set)"
+        b.set_shape(kib, 16)
+        assert b.plan()[3] == f"zq={kib} pre=16 (set)"
     b.sweep(SWEEPS)
     b.sync()
     out = [b.chain(i).draws() for i in range(len(b))]
@@ -89,8 +89,8 @@ def test_queue_setting_is_checked(env, data):
     torch, hsp = env
     d, xt, _ = data[1]
     b = hsp.Batch([(torch.from_numpy(d.X).cuda(), torch.from_numpy(d.y).cuda(), xt)], 2, seed=1)
-    for bad in (-1, 4097):
+    for bad in ((-1, 16), (4097, 16), (64, -1), (64, 4097)):
         with pytest.raises(hsp.HspError) as e:
-            b.set_zqueue(bad)
+            b.set_shape(*bad)
         assert e.value.code == hsp.HSP_EINVAL
     b.close()
