@@ -51,12 +51,13 @@ constexpr int kZGroup = 16;            // z-pass blocks whose partials one block
 // whole rows (up to 1536 float32 or 1024 bfloat16 elements) or the row is
 // split over the block's four waves, and the rows per tile.  Both are set by
 // the register budget of two blocks per compute unit: a taller tile or a
-// whole wider row in one wave spills.  Short rows get tall tiles (16 rows up
-// to 512 float32 or bfloat16 elements): a tile's loads, its wave reductions
-// and its truncated-normal draws (one lane per row) then cover twice the rows.
+// whole wider row in one wave spills.  Short rows get tall tiles (32 rows up
+// to 256 float32 elements, 16 up to 512 float32 or bfloat16 elements): a
+// tile's loads and its truncated-normal draws (one lane per row) then cover
+// more rows at once.
 constexpr bool wide_chunks(int xtype, int kc) { return xtype == 0 ? kc > 6 : kc > 2; }
 constexpr int rows_for(int xtype, int kc) {
-    if (!wide_chunks(xtype, kc)) return kc <= (xtype == 0 ? 2 : 1) ? 16 : kc <= 4 ? 8 : 4;
+    if (!wide_chunks(xtype, kc)) return kc == 1 && xtype == 0 ? 32 : kc <= (xtype == 0 ? 2 : 1) ? 16 : kc <= 4 ? 8 : 4;
     const int kcw = (kc + 3) / 4;  // chunks per lane of each wave's quarter
     return xtype == 0 ? (kcw <= 3 ? 4 : kcw <= 7 ? 2 : 1) : (kcw <= 2 ? 4 : kcw <= 4 ? 2 : 1);
 }

@@ -97,13 +97,13 @@ def test_batch_chain_equals_lone_chain(env):
 
 
 def test_batch_mixed_tile_heights_equal_lone_chains(env):
-    """Float32 chains with 257 <= p <= 512 (16-row z tiles), 513 <= p <=
-    1024 (8-row tiles) and p > 1024 (4-row tiles) in one batch, with
+    """Float32 chains with p <= 256 (32-row z tiles), 257 <= p <= 512 (16
+    rows), 513 <= p <= 1024 (8 rows) and p > 1024 (4 rows) in one batch, with
     bfloat16 chains: each pack keeps one tile height, so every chain still
     draws bitwise what it draws alone."""
     torch, hsp = env
     sets = [((2003, 1000, 66), "f32", 1), ((2003, 1100, 67), "f32", 1), ((1500, 300, 68), "f32", 1),
-            ((1500, 2100, 69), "bf16", 1), ((1800, 700, 70), "bf16", 1)]
+            ((1500, 2100, 69), "bf16", 1), ((1800, 700, 70), "bf16", 1), ((2222, 150, 71), "f32", 1)]
     ds, b = make_batch(env, sets, seed=6, chain_id=2)
     b.sweep(3)
     b.sync()
