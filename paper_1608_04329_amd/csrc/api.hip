@@ -968,6 +968,9 @@ struct Pack {
     int xtype = 0;
     int chunks = 1;  // 16-byte vectors per lane per row: the largest of the pack's chains
     uint32_t blocks = 0;
+    uint32_t waiting = 0;   // blocks that wait on other blocks of the launch (the p-side groups)
+    double bytes = 0.0;     // X read per sweep
+    int capacity = 0;       // resident blocks of the pack's kernel on the device
     // chains sharing one bfloat16 design: a multi-chain z pass (its own
     // launch, mc_gz blocks) precedes the launch of their p-side groups
     bool mc = false;
@@ -1012,7 +1015,7 @@ struct hsp_batch {
     bool overlap = true;       // multi-chain passes on a second stream, beside the other packs
     uint32_t pre_gp = 0;       // blocks per chain factoring Q beside the multi-chain pass (0: after it)
     hipStream_t side = nullptr, side2 = nullptr;  // streams of the passes and of the pre packs
-    hipEvent_t fork = nullptr, join = nullptr, join2 = nullptr;  // (captured into the graph only)
+    hipEvent_t fork = nullptr, join = nullptr, join2 = nullptr, join3 = nullptr;  // (captured into the graph only)
     bool autotune = false;
     std::string plan_note = "built-in";
 };
@@ -1044,6 +1047,7 @@ void free_batch(hsp_batch* b) {
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->join) (void)hipEventDestroy(b->join);
     if (b->join2) (void)hipEventDestroy(b->join2);
+    if (b->join3) (void)hipEventDestroy(b->join3);
     if (b->side) (void)hipStreamDestroy(b->side);
     if (b->side2) (void)hipStreamDestroy(b->side2);
     b->timer.reset();
@@ -1346,6 +1350,14 @@ hsp_status plan_packs(hsp_batch* b) {
             for (uint32_t q = 0; q < h.gp + h.gz; ++q) map[blk + q] = (uint16_t)j;
             blk += h.gp + h.gz;
         }
+        pk.waiting = 0;
+        pk.bytes = 0.0;
+        for (size_t j = 0; j < nc; ++j) {
+            const hsp_state* s = b->chains[pk.chains[j]];
+            pk.waiting += pk.gp[j];
+            if (!pk.pre) pk.bytes += (double)s->x.N * s->x.ld * (s->x.xtype == 0 ? 4 : 2);
+        }
+        pk.capacity = pack_capacity(pk.xtype, pk.chunks, b->chains[0]->num_cus);
         if (pk.queue) {
             // the workers follow every p-side group
             for (uint32_t w = 0; w < pk.workers; ++w) map[blk + w] = (uint16_t)(kWorkerBit | pk.home[w]);
@@ -1388,14 +1400,20 @@ hsp_status batch_build(hsp_batch* b) {
         if (st != HSP_OK) return st;
     }
     if (b->graph) return HSP_OK;
-    bool any_mc = false, any_plain = false, any_pre = false;
-    for (const Pack& pk : b->packs) (pk.pre ? any_pre : pk.mc ? any_mc : any_plain) = true;
-    const bool overlap = b->overlap && any_mc && (any_plain || any_pre);
+    bool any_mc = false, any_pre = false;
+    size_t n_plain = 0;
+    for (const Pack& pk : b->packs) {
+        if (pk.pre) any_pre = true;
+        else if (pk.mc) any_mc = true;
+        else ++n_plain;
+    }
+    const bool overlap = b->overlap && ((any_mc && (n_plain > 0 || any_pre)) || n_plain > 1);
     hipError_t e = hipSuccess;
     if (overlap && !b->side) {
         e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
         if (!e) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
         if (!e) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+        if (!e) e = hipEventCreateWithFlags(&b->join3, hipEventDisableTiming);
         if (e) return batch_fail(b, HSP_EHIP, std::string("batch side stream: ") + hipGetErrorString(e));
     }
     if (overlap && any_pre && !b->side2) {
@@ -1425,12 +1443,29 @@ hsp_status batch_build(hsp_batch* b) {
                 if (b->packs[i].pre) e = launch(b->packs[i], b->side2);
             if (!e) e = hipEventRecord(b->join2, b->side2);
         }
-        for (size_t i = 0; !e && i < b->packs.size(); ++i)
-            if (!b->packs[i].mc && !b->packs[i].pre) e = launch(b->packs[i], b->stream);
+        // The other packs: the one with the most X on the batch's stream, the
+        // rest after the passes on theirs, if every launch that may then be
+        // resident at once leaves at least half of the device to blocks that
+        // never wait.
+        std::vector<size_t> plain;
+        int waiting = 0, cap = 0;
+        for (size_t i = 0; i < b->packs.size(); ++i) {
+            const Pack& pk = b->packs[i];
+            if (!pk.mc) waiting += (int)pk.waiting;  // pre packs wait inside too
+            if (!pk.mc && !pk.pre) plain.push_back(i);
+            cap = cap ? std::min(cap, pk.capacity) : pk.capacity;
+        }
+        std::stable_sort(plain.begin(), plain.end(),
+                         [&](size_t x, size_t y) { return b->packs[x].bytes > b->packs[y].bytes; });
+        const bool spread = plain.size() > 1 && 2 * waiting <= cap;
+        for (size_t k = 0; !e && k < plain.size(); ++k)
+            e = launch(b->packs[plain[k]], spread && k > 0 ? b->side : b->stream);
+        if (!e && spread) e = hipEventRecord(b->join3, b->side);
         if (!e) e = hipStreamWaitEvent(b->stream, b->join, 0);
         if (!e && any_pre) e = hipStreamWaitEvent(b->stream, b->join2, 0);
         for (size_t i = 0; !e && i < b->packs.size(); ++i)
             if (b->packs[i].mc) e = launch(b->packs[i], b->stream);
+        if (!e && spread) e = hipStreamWaitEvent(b->stream, b->join3, 0);
     } else {
         // in pack order: a pre pack comes just before its multi-chain pack
         for (size_t i = 0; !e && i < b->packs.size(); ++i) {
