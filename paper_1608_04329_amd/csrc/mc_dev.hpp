@@ -158,20 +158,17 @@ __device__ void mc_role(McView& m, uint32_t rank, double* lds) {
     // tile t's X (16-byte loads) and the outcome of the row this thread draws
     U32x4 xr[KS];
     uint32_t ypre = 0;
+    // Every lane loads, with no branch: a row past the last reads the last
+    // row (its z is 0, so it adds nothing to X^T z) and a column past the
+    // last reads the row's last 16 bytes (beta is 0 there, and those columns
+    // of the partial are never read), so each product is the one zeros give.
     auto load_tile = [&](uint32_t t) {
-        {
-            const uint32_t yr = t * kMcRows + (threadIdx.x >> 4);
-            ypre = yr < N ? (uint32_t)m.y[yr] : 0u;
-        }
-        const uint32_t row = t * kMcRows + (uint32_t)n;
+        ypre = (uint32_t)m.y[min(t * kMcRows + (threadIdx.x >> 4), N - 1u)];
+        const char* rowp = Xb + (size_t)min(t * kMcRows + (uint32_t)n, N - 1u) * row_bytes;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-            const uint32_t col = 32u * (ks0 + s) + 8u * q;
-            if (row < N && col < ld)
-                xr[s] = __builtin_nontemporal_load(
-                    reinterpret_cast<const U32x4*>(Xb + row * row_bytes + (size_t)col * 2));
-            else
-                xr[s] = U32x4{0u, 0u, 0u, 0u};
+            const uint32_t col = min(32u * (ks0 + s) + 8u * q, ld - 8u);
+            xr[s] = __builtin_nontemporal_load(reinterpret_cast<const U32x4*>(rowp + (size_t)col * 2));
         }
     };
 
