@@ -136,7 +136,7 @@ void hsp_default_options(hsp_options* opt);
 hsp_status hsp_create(const float* X, const uint8_t* y, int64_t N, int64_t p,
                       const hsp_options* opt, hsp_state** out);
 
-/* Largest p supported by this build. */
+/* Largest p the library supports. */
 int64_t hsp_max_p(void);
 
 /*
