@@ -209,6 +209,8 @@ SweepArgs sweep_args(hsp_state* s, uint32_t mode) {
     a.timeout_ticks = s->timeout_ticks;
     a.trace = dev_ptr(s->trace);
     a.gp = a.gz = a.zgroups = a.block0 = 0;
+    const uint32_t nt = (s->x.p + kTile - 1) / kTile;
+    a.subst = s->x.p > (uint32_t)kSmallP && !with_inverse(nt) ? 1u : 0u;
     return a;
 }
 
@@ -846,8 +848,9 @@ hsp_status chain_impl(hsp_state* s) {
     if (p > kSmallP) {
         // the factorisation's task lists for the group, and its tile versions
         const uint32_t nt = (uint32_t)(P / kTile);
-        HIP_TRY(dalloc(&s->ver, 2 * (size_t)nt * nt));
-        HIP_TRY(hipMemsetAsync(s->ver, 0, 2 * (size_t)nt * nt * 4, s->stream));
+        // tile versions, then the substitution's 2 nt row flags (p > kLargeP)
+        HIP_TRY(dalloc(&s->ver, 2 * (size_t)nt * nt + 2 * (size_t)nt));
+        HIP_TRY(hipMemsetAsync(s->ver, 0, (2 * (size_t)nt * nt + 2 * (size_t)nt) * 4, s->stream));
         hsp_status st = upload_schedule(s);
         if (st) return st;
     }

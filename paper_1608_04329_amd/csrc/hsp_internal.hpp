@@ -178,6 +178,7 @@ struct SweepArgs {
                              // y, the Philox counters and the debug outputs use global rows
     HSP_GLOBAL const uint32_t* row_id;  // original index of each stored row (rows reordered), or null
     HSP_GLOBAL PackQ* zq;  // the pack's shared z queue, or null (then gz blocks of its own)
+    uint32_t subst;        // tile path: beta by blocked substitution (factorisation without L^-1)
 };
 
 // ---- the shared z queue of a pack -----------------------------------------------
@@ -255,6 +256,12 @@ __host__ __device__ constexpr uint32_t task_code(uint32_t type, uint32_t part, u
 // (schedule.cpp): with gp = 1 one list, tasks[off[0] .. off[1]), run in order by
 // block 0; with gp > 1 block 0's chain list tasks[off[0] .. off[1]) and the
 // shared queue tasks[off[1] .. off[2]) the other blocks claim in order.
+// Whether the factorisation of nt tiles per side carries L^-1 = U^-T along
+// (beta as two parallel triangular products) or leaves it out beyond the
+// diagonal tiles (beta by blocked substitution): beyond p = kLargeP the
+// products' L^-1 would cost half of the factorisation's flops, far more than
+// the substitution's latency.
+constexpr bool with_inverse(uint32_t nt) { return nt * (uint32_t)kTile <= (uint32_t)kLargeP; }
 void chol_schedule(uint32_t nt, uint32_t gp, std::vector<uint32_t>* tasks,
                    std::vector<uint32_t>* off);
 

@@ -864,6 +864,126 @@ __device__ bool run_tasks(Args& a, Group& g, uint32_t rank, double tau, Tile& S,
     return true;
 }
 
+// beta = U^-1 (U^-T b + s) by blocked substitution (p > kLargeP: there the
+// factorisation leaves L^-1 out beyond its diagonal tiles, half of its flops).
+// Block r of the group owns tile rows r, r + gp, ...  Forward, its rows in
+// increasing order: the owner of row i subtracts U_ki^T w_k from b_i for each
+// k < i as soon as row k's flag is up, then w_i = L^-1_ii r_i (the diagonal
+// tile of L^-1 the factorisation stored), stores it and raises row i's flag.
+// Backward, its rows in decreasing order: r_i = w_i + s_i - sum_{k > i}
+// U_ik beta_k, beta_i = U_ii^-1 r_i = (L^-1_ii)^T r_i.  A row waits only on
+// rows finished before it in the same direction, so the solve cannot
+// deadlock.  Flags sit after the tile versions and are cleared with them.
+__device__ void subst_solve(Args& a, Group& g, uint32_t rank, uint32_t k, double* lds, bool from_sum) {
+    const uint32_t p = a.x.p, P = padded(p), nt = P / kTile;
+    uint32_t* ff = a.ver + 2 * nt * nt;  // forward: w_i stored
+    uint32_t* fb = ff + nt;              // backward: beta_i stored
+    double* yv = a.vec;                  // w (then read back for y = w + s)
+    const double* s_noise = a.vec + p;
+    double* rv = lds;                    // the owned row's running vector (64)
+    double* part = lds + kTile;          // 4 x 64 partial sums
+    double* flag = lds + 5 * kTile;
+    const int c = threadIdx.x & (kTile - 1), q = threadIdx.x >> 6;
+    auto b_at = [&](uint32_t j) -> double {
+        if (j >= p) return 0.0;
+        return from_sum ? ldc(&a.bsum[j]) * a.xscale[j] : a.b[j];
+    };
+    auto wait_row = [&](uint32_t* f) -> bool {
+        if (threadIdx.x == 0) {
+            uint32_t* v[3] = {f, nullptr, nullptr};
+            const uint32_t need[3] = {1u, 0u, 0u};
+            *flag = wait_vers(v, need, 1, a.ctrl, g.timeout) ? 0.0 : 1.0;
+        }
+        __syncthreads();
+        return *flag == 0.0;
+    };
+    // rv -= the four partial sums (then every thread sees the new rv)
+    auto fold = [&](double acc) {
+        part[q * kTile + c] = acc;
+        __syncthreads();
+        if (threadIdx.x < (uint32_t)kTile)
+            rv[c] -= (part[c] + part[kTile + c]) + (part[2 * kTile + c] + part[3 * kTile + c]);
+        __syncthreads();
+    };
+    bool ok = true;
+    for (uint32_t i = rank; ok && i < nt; i += g.size) {
+        const uint32_t i0 = i * kTile;
+        if (threadIdx.x < (uint32_t)kTile) rv[c] = b_at(i0 + c);
+        __syncthreads();
+        for (uint32_t kk = 0; ok && kk < i; ++kk) {
+            if (!(ok = wait_row(&ff[kk]))) break;
+            // (U_kk,i^T w_kk)_c: thread (q, c) sums rows q, q + 4, ... of the tile
+            double acc = 0.0;
+#pragma unroll 4
+            for (int j = 0; j < 16; ++j) {
+                const uint32_t row = kk * kTile + q + 4 * j;
+                const double wv = row < p ? ldc(&yv[row]) : 0.0;
+                acc = fma(ldc(&a.A[(size_t)row * P + i0 + c]), wv, acc);
+            }
+            fold(acc);
+        }
+        if (!ok) break;
+        // w_i = L^-1_ii r: thread (q, c) takes row c's columns 16 q .. 16 q + 15
+        double acc = 0.0;
+#pragma unroll 4
+        for (int j = 0; j < 16; ++j)
+            acc = fma(ldc(&a.Linv[(size_t)(i0 + c) * P + i0 + 16 * q + j]), rv[16 * q + j], acc);
+        part[q * kTile + c] = acc;
+        __syncthreads();
+        if (threadIdx.x < (uint32_t)kTile && i0 + c < p)
+            stc(&yv[i0 + c], (part[c] + part[kTile + c]) + (part[2 * kTile + c] + part[3 * kTile + c]));
+        publish(&ff[i], 1u);
+    }
+    bool keep;
+    const uint32_t slot = record_slot(a, k, &keep);
+    bool nonfinite = false;
+    const uint32_t nown = rank < nt ? (nt - 1 - rank) / g.size + 1 : 0u;
+    for (uint32_t o = nown; ok && o-- > 0;) {
+        const uint32_t i = rank + o * g.size, i0 = i * kTile;
+        if (threadIdx.x < (uint32_t)kTile) rv[c] = i0 + c < p ? ldc(&yv[i0 + c]) + ldc(&s_noise[i0 + c]) : 0.0;
+        __syncthreads();
+        for (uint32_t kk = nt - 1; ok && kk > i; --kk) {
+            if (!(ok = wait_row(&fb[kk]))) break;
+            // (U_i,kk beta_kk)_c: thread (q, c) takes row c's columns 16 q .. 16 q + 15
+            double acc = 0.0;
+#pragma unroll 4
+            for (int j = 0; j < 16; ++j) {
+                const uint32_t col = kk * kTile + 16 * q + j;
+                const double bv = col < p ? ldc(&a.beta[col]) : 0.0;
+                acc = fma(ldc(&a.A[(size_t)(i0 + c) * P + col]), bv, acc);
+            }
+            fold(acc);
+        }
+        if (!ok) break;
+        // beta_i = (L^-1_ii)^T r: thread (q, c) sums rows q, q + 4, ... of column c
+        double acc = 0.0;
+#pragma unroll 4
+        for (int j = 0; j < 16; ++j) {
+            const uint32_t r = q + 4 * j;
+            acc = fma(ldc(&a.Linv[(size_t)(i0 + r) * P + i0 + c]), rv[r], acc);
+        }
+        part[q * kTile + c] = acc;
+        __syncthreads();
+        if (threadIdx.x < (uint32_t)kTile && i0 + c < p) {
+            const uint32_t col = i0 + c;
+            const double bi = (part[c] + part[kTile + c]) + (part[2 * kTile + c] + part[3 * kTile + c]);
+            stc(&a.beta[col], bi);
+            a.beta32[col] = (float)(bi * a.xscale[col]);
+            if (!isfinite(bi)) nonfinite = true;
+            if (keep) {
+                a.ring_beta[(size_t)slot * p + col] = bi;
+                if (a.ring_lam) a.ring_lam[(size_t)slot * p + col] = ldc(&a.lam_m2[col]);
+            }
+        }
+        publish(&fb[i], 1u);
+    }
+    if (nonfinite) atomicOr(&a.ctrl->err, kErrNonFinite);
+    if (keep && rank == 0 && threadIdx.x == 0) a.ring_tau[slot] = current_tau(a);
+    // no block leaves before every flag it may wait on is up: the launch's
+    // closing block clears them after this barrier
+    group_sync(g);
+}
+
 __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* lds) {
     const uint32_t p = a.x.p, P = padded(p);
     Tile& S = *reinterpret_cast<Tile*>(lds);
@@ -920,7 +1040,9 @@ __device__ void tile_path(Args& a, Group& g, uint32_t rank, uint32_t k, double* 
     }
     __syncthreads();
 
-    if ((a.mode & kModeBeta) && ok) {
+    if ((a.mode & kModeBeta) && ok && a.subst) {
+        subst_solve(a, g, rank, k, lds, from_sum);
+    } else if ((a.mode & kModeBeta) && ok) {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         // y = L^-1 b + s, four rows per wave at a time.  L^-1 is zero above the
         // diagonal and the identity on the padding, and b is zero there, so
@@ -1052,7 +1174,9 @@ __device__ __forceinline__ void pside_role(Args& a, uint32_t rank, uint32_t k, d
         }
         if (a.x.p > (uint32_t)kSmallP && (a.mode & kModeBeta) && !(a.mode & kModePost)) {
             const uint32_t nt = padded(a.x.p) / kTile;
-            for (uint32_t e = threadIdx.x; e < 2 * nt * nt; e += kThreads) a.ver[e] = 0u;
+            // tile versions, and the substitution's row flags after them
+            const uint32_t nver = 2 * nt * nt + (a.subst ? 2 * nt : 0u);
+            for (uint32_t e = threadIdx.x; e < nver; e += kThreads) a.ver[e] = 0u;
             if (threadIdx.x == 0) a.ctrl->task_next = 0u;
         }
         if (a.mode & (kModeZ | kModeBsum)) {

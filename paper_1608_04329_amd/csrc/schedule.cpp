@@ -1,4 +1,5 @@
 // Static list schedule of the tiled factorisation of [Q | I] (host side).
+// (Beyond p = kLargeP the L^-1 tasks are left out: see with_inverse.)
 //
 // The factorisation of Q = U^T U by 64 x 64 tiles, with the same row
 // operations applied to an identity block so that L^-1 = U^-T comes out too,
@@ -53,6 +54,7 @@ void chol_schedule(uint32_t nt, uint32_t gp, std::vector<uint32_t>* tasks,
     // rough costs in units of one tile task
     const double c_potrf = 3.5, c_panel = 4.5, c_trsm = 1.0, c_gemm = 1.0;
     const bool chain = gp > 1;  // block 0 owns the critical chain
+    const bool inv = with_inverse(nt);  // the L^-1 tasks (TRSM_L, GEMM_L) are part of the graph
     std::vector<Task> t;
     auto idx3 = [nt](uint32_t k, uint32_t i, uint32_t j) { return ((size_t)k * nt + i) * nt + j; };
     // ids: potrf[k] (k = 0, or every k without a chain block), panel[k] (k >= 1 with one),
@@ -82,12 +84,13 @@ void chol_schedule(uint32_t nt, uint32_t gp, std::vector<uint32_t>* tasks,
         }
         for (uint32_t j = k + 1; j < nt; ++j)
             if (!(chain && j == k + 1)) trsm_u[k * nt + j] = add(task_code(kTaskTrsm, 0, k, k, j), c_trsm, false);
-        for (uint32_t j = 0; j < k; ++j) trsm_l[k * nt + j] = add(task_code(kTaskTrsm, 1, k, k, j), c_trsm, false);
+        for (uint32_t j = 0; inv && j < k; ++j) trsm_l[k * nt + j] = add(task_code(kTaskTrsm, 1, k, k, j), c_trsm, false);
         for (uint32_t i = k + 1; i < nt; ++i) {
             for (uint32_t j = i; j < nt; ++j)
                 if (!(chain && i == k + 1 && j == k + 1))
                     gemm_u[idx3(k, i, j)] = add(task_code(kTaskGemm, 0, k, i, j), c_gemm, false);
-            for (uint32_t j = 0; j <= k; ++j) gemm_l[idx3(k, i, j)] = add(task_code(kTaskGemm, 1, k, i, j), c_gemm, false);
+            for (uint32_t j = 0; inv && j <= k; ++j)
+                gemm_l[idx3(k, i, j)] = add(task_code(kTaskGemm, 1, k, i, j), c_gemm, false);
         }
     }
     // trsm_u[k][k+1] and gemm_u[k][k+1][k+1] are created with step k + 1's panel
@@ -111,7 +114,7 @@ void chol_schedule(uint32_t nt, uint32_t gp, std::vector<uint32_t>* tasks,
             dep(potrf[k], trsm_u[k * nt + j]);
             if (k > 0) dep(gemm_u[idx3(k - 1, k, j)], trsm_u[k * nt + j]);
         }
-        for (uint32_t j = 0; j < k; ++j) {
+        for (uint32_t j = 0; inv && j < k; ++j) {
             dep(potrf[k], trsm_l[k * nt + j]);
             dep(gemm_l[idx3(k - 1, k, j)], trsm_l[k * nt + j]);
         }
@@ -122,7 +125,7 @@ void chol_schedule(uint32_t nt, uint32_t gp, std::vector<uint32_t>* tasks,
                 if (j != i) dep(trsm_u[k * nt + j], g);
                 if (k > 0) dep(gemm_u[idx3(k - 1, i, j)], g);
             }
-            for (uint32_t j = 0; j <= k; ++j) {
+            for (uint32_t j = 0; inv && j <= k; ++j) {
                 const int64_t g = gemm_l[idx3(k, i, j)];
                 dep(trsm_u[k * nt + i], g);
                 dep(j == k ? potrf[k] : trsm_l[k * nt + j], g);
