@@ -479,6 +479,12 @@ hsp_status tune_impl(hsp_state* s) {
             const uint32_t g = std::max<uint32_t>(1, (gmax * pct + 50) / 100);
             if (std::find(gps.begin(), gps.end(), g) == gps.end()) gps.push_back(g);
         }
+    // where the factorisation was judged to outweigh the pass, the smaller
+    // group that would otherwise be chosen is tried as well
+    if (!large && s->x.p > (uint32_t)kSmallP) {
+        const uint32_t q = std::max<uint32_t>(1, std::min<uint32_t>(kMaxGroup, (uint32_t)s->plan.capacity / 4));
+        if (q < gmax && std::find(gps.begin(), gps.end(), q) == gps.end()) gps.push_back(q);
+    }
     const std::vector<uint32_t> pcts = large ? std::vector<uint32_t>{kZStaticPctDefault}
                                              : std::vector<uint32_t>{0u, 40u, 75u};
     const std::vector<uint32_t> units = large ? std::vector<uint32_t>{kZUnitDefault}
@@ -848,7 +854,7 @@ hsp_status chain_impl(hsp_state* s) {
     if (p > kSmallP) {
         // the factorisation's task lists for the group, and its tile versions
         const uint32_t nt = (uint32_t)(P / kTile);
-        // tile versions, then the substitution's 2 nt row flags (p > kLargeP)
+        // tile versions, then the substitution's 2 nt row flags (p > kSubstP)
         HIP_TRY(dalloc(&s->ver, 2 * (size_t)nt * nt + 2 * (size_t)nt));
         HIP_TRY(hipMemsetAsync(s->ver, 0, (2 * (size_t)nt * nt + 2 * (size_t)nt) * 4, s->stream));
         hsp_status st = upload_schedule(s);

@@ -258,10 +258,14 @@ __host__ __device__ constexpr uint32_t task_code(uint32_t type, uint32_t part, u
 // shared queue tasks[off[1] .. off[2]) the other blocks claim in order.
 // Whether the factorisation of nt tiles per side carries L^-1 = U^-T along
 // (beta as two parallel triangular products) or leaves it out beyond the
-// diagonal tiles (beta by blocked substitution): beyond p = kLargeP the
-// products' L^-1 would cost half of the factorisation's flops, far more than
-// the substitution's latency.
-constexpr bool with_inverse(uint32_t nt) { return nt * (uint32_t)kTile <= (uint32_t)kLargeP; }
+// diagonal tiles (beta by blocked substitution).  L^-1 is half of the
+// factorisation's flops; up to p = kSubstP the factorisation hides under the
+// z pass and the products make the shorter tail, beyond it the substitution's
+// latency costs less (measured: N = 1e6, p = 1500: 1.10 ms per sweep with L^-1
+// against 1.23 ms; N = 5e5, p = 2048: 1.66 against 1.29 ms; N = 2e5, p = 4096:
+// 11.5 against 6.5 ms).
+constexpr int kSubstP = 1536;
+constexpr bool with_inverse(uint32_t nt) { return nt * (uint32_t)kTile <= (uint32_t)kSubstP; }
 void chol_schedule(uint32_t nt, uint32_t gp, std::vector<uint32_t>* tasks,
                    std::vector<uint32_t>* off);
 

@@ -864,7 +864,7 @@ __device__ bool run_tasks(Args& a, Group& g, uint32_t rank, double tau, Tile& S,
     return true;
 }
 
-// beta = U^-1 (U^-T b + s) by blocked substitution (p > kLargeP: there the
+// beta = U^-1 (U^-T b + s) by blocked substitution (p > kSubstP: there the
 // factorisation leaves L^-1 out beyond its diagonal tiles, half of its flops).
 // Block r of the group owns tile rows r, r + gp, ...  Forward, its rows in
 // increasing order: the owner of row i subtracts U_ki^T w_k from b_i for each

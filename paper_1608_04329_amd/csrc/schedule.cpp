@@ -1,5 +1,5 @@
 // Static list schedule of the tiled factorisation of [Q | I] (host side).
-// (Beyond p = kLargeP the L^-1 tasks are left out: see with_inverse.)
+// (Beyond p = kSubstP the L^-1 tasks are left out: see with_inverse.)
 //
 // The factorisation of Q = U^T U by 64 x 64 tiles, with the same row
 // operations applied to an identity block so that L^-1 = U^-T comes out too,

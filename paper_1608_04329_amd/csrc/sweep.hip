@@ -96,12 +96,21 @@ KernelFn kernel_for(int xtype, int chunks) {
 uint32_t max_group(const XLayout& x, int capacity) {
     const uint32_t nt = (x.p + kTile - 1) / kTile;
     uint32_t gp = x.p <= (uint32_t)kSmallP ? 1u : nt * (nt + 1) / 2;
-    if (x.p <= kLargeP) {
+    // the factorisation's tile tasks (each ~6 us on one block) against the
+    // pass over X (~6 TB/s) on the other three quarters of the device
+    double tasks = 0.0;
+    for (uint32_t k = 0; x.p > (uint32_t)kSmallP && k < nt; ++k) {
+        const double m = nt - k - 1;
+        tasks += 1.0 + m + m * (m + 1.0) / 2.0 + (with_inverse(nt) ? k + m * (k + 1.0) : 0.0);
+    }
+    const double z_us = (double)x.N * x.ld * (x.xtype == 0 ? 4 : 2) / 6.0e6;
+    const bool factor_bound = tasks * 6.0 / (kMaxGroup - 1) > z_us;
+    if (x.p <= kLargeP && !factor_bound) {
         // the factorisation hides under the z pass: a quarter of the device at most
         if (gp > (uint32_t)kMaxGroup) gp = kMaxGroup;
         if (gp > (uint32_t)capacity / 4) gp = capacity / 4 > 0 ? capacity / 4 : 1;
     } else {
-        // p^3 / 3 flops per sweep outweigh the pass over X: three quarters
+        // the factorisation outweighs the pass over X: three quarters
         const uint32_t cap = (uint32_t)capacity * 3 / 4;
         if (gp > cap) gp = cap > 0 ? cap : 1;
     }

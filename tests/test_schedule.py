@@ -24,9 +24,9 @@ def decode(c):
 
 
 def with_inverse(nt):
-    """L^-1 is carried along up to p = 4096 (64 tiles); beyond, beta is solved
+    """L^-1 is carried along up to p = 1536 (24 tiles); beyond, beta is solved
     by substitution and only the diagonal tiles of L^-1 are formed."""
-    return nt * 64 <= 4096
+    return nt * 64 <= 1536
 
 
 def expected_tasks(nt, chain):
@@ -146,8 +146,8 @@ def lists_of(nt, gp):
     return dec[off[0]:off[1]], dec[off[1]:off[2]], gp - 1
 
 
-@pytest.mark.parametrize("nt,gp", [(1, 1), (2, 1), (3, 2), (5, 32), (16, 32), (16, 7), (20, 32), (40, 96),
-                                   (64, 96), (65, 96), (70, 384)])
+@pytest.mark.parametrize("nt,gp", [(1, 1), (2, 1), (3, 2), (5, 32), (16, 32), (16, 7), (20, 32), (24, 48),
+                                   (25, 48), (40, 96), (70, 384)])
 def test_schedule_covers_every_task_and_never_deadlocks(nt, gp):
     tasks, off = hsp.hsp_tile_schedule(nt, gp)
     assert off[0] == 0 and off[-1] == len(tasks) and np.all(np.diff(off.astype(np.int64)) >= 0)
