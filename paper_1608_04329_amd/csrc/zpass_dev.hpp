@@ -128,7 +128,14 @@ __device__ __forceinline__ void z_tile(Args& a, uint32_t t, uint32_t ksweep,
                 xr[r][kc] = make_uint4(0u, 0u, 0u, 0u);
         }
 
-    // eta for the R rows of the tile, reduced across the wave
+    // eta for the R rows of the tile, reduced across the wave.  While a lane
+    // holds more than one row, each exchange step halves them: the lane's bit
+    // of the step picks the half it keeps, the partner lane keeps the other,
+    // and each adds the half it receives, so the R rows cost R - 1 exchanges
+    // instead of 6 R.  Once one row is left the steps are plain pairwise sums.
+    // Lane l ends with the whole sum of row l >> (6 - log2 R).
+    static_assert(R >= 1 && R <= kWave && (R & (R - 1)) == 0, "rows per tile: a power of two");
+    constexpr int LR = R >= 32 ? 5 : R >= 16 ? 4 : R >= 8 ? 3 : R >= 4 ? 2 : R >= 2 ? 1 : 0;
     float s[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -140,30 +147,38 @@ __device__ __forceinline__ void z_tile(Args& a, uint32_t t, uint32_t ksweep,
         s[r] = acc;
     }
 #pragma unroll
-    for (int off = kWave / 2; off >= 1; off >>= 1)
+    for (int st = 0; st < 6; ++st) {
+        const int off = kWave >> (st + 1);
+        const int h = R >> (st + 1);  // rows kept after this step (0: one row left)
+        if (h >= 1) {
+            const bool up = (lane & off) != 0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) s[r] += __shfl_xor(s[r], off);
+            for (int j = 0; j < h; ++j) {
+                const float send = up ? s[j] : s[j + h];
+                const float keep = up ? s[j + h] : s[j];
+                s[j] = keep + __shfl_xor(send, off);
+            }
+        } else {
+            s[0] += __shfl_xor(s[0], off);
+        }
+    }
+    float eta;
     if constexpr (WIDE) {
         // the four quarters' sums through LDS, added in wave order; the
         // two slots alternate, so one barrier per tile keeps a slot from
         // being rewritten before every wave has read it
         double* slotp = eta_lds + parity * (kWPB * R);
-        if (lane == 0)
-#pragma unroll
-            for (int r = 0; r < R; ++r) slotp[wave * R + r] = (double)s[r];
+        if ((lane & ((1 << (6 - LR)) - 1)) == 0) slotp[wave * R + (lane >> (6 - LR))] = (double)s[0];
         __syncthreads();
+        const int rr = lane < R ? lane : 0;
+        float v = (float)slotp[rr];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            float v = (float)slotp[r];
-#pragma unroll
-            for (int w = 1; w < kWPB; ++w) v += (float)slotp[w * R + r];
-            s[r] = v;
-        }
+        for (int w = 1; w < kWPB; ++w) v += (float)slotp[w * R + rr];
+        eta = v;
         parity ^= 1u;
+    } else {
+        eta = __shfl(s[0], lane << (6 - LR));  // row `lane`'s sum, for lanes below R
     }
-    float eta = s[0];
-#pragma unroll
-    for (int r = 1; r < R; ++r) eta = (lane == r) ? s[r] : eta;
 
     // lane r < R draws z for row row0 + r: position first_row + row0 + r of
     // the stored X and y (X may arrive in row chunks), whose original row
