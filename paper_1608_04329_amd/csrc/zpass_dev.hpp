@@ -108,25 +108,36 @@ __device__ __forceinline__ void z_tile(Args& a, uint32_t t, uint32_t ksweep,
     const char* __restrict__ Xb = static_cast<const char*>(a.x.X);
     const size_t row_bytes = (size_t)ld * EB;
     const uint32_t c0 = WIDE ? (uint32_t)wave * KC * CW : 0u;
-    const uint32_t row0 = t * R;
+    // The tile index is the same in every lane, so the row addresses are
+    // scalar: each load is a scalar row base plus the lane's 32-bit column
+    // offset.  Rows past the end are read as the last row and columns past
+    // the row's end as its last chunk, so no load is predicated: those
+    // elements meet a zero beta (no part in eta) and a zero z (rows past the
+    // end are not drawn), and their column sums are never written out.
+    const uint32_t row0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)t) * (uint32_t)R;
+    uint32_t coff[KC];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) coff[kc] = min(c0 + kc * CW + lane * VEC, ld - VEC) * EB;
     uint4 xr[R][KC];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+    for (int r = 0; r < R; ++r) {
+        const uint64_t ra = (uint64_t)(uintptr_t)Xb + (uint64_t)min(row0 + r, N - 1) * row_bytes;
+        // (the builtin returns a signed int: each half goes through uint32_t
+        // so that the low half is not sign-extended into the high one)
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(ra >> 32));
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)ra);
+        const HSP_GLOBAL char* rp = reinterpret_cast<const HSP_GLOBAL char*>(((uint64_t)hi << 32) | (uint64_t)lo);
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
-            const uint32_t row = row0 + r;
-            const uint32_t col = c0 + kc * CW + lane * VEC;
-            if (row < N && col < ld) {
+            const HSP_GLOBAL U32x4* src = reinterpret_cast<const HSP_GLOBAL U32x4*>(rp + coff[kc]);
 #if HSP_X_NONTEMPORAL
-                const U32x4 v = __builtin_nontemporal_load(
-                    reinterpret_cast<const U32x4*>(Xb + row * row_bytes + (size_t)col * EB));
-                xr[r][kc] = make_uint4(v.x, v.y, v.z, v.w);
+            const U32x4 v = __builtin_nontemporal_load(src);
 #else
-                xr[r][kc] = *reinterpret_cast<const uint4*>(Xb + row * row_bytes + (size_t)col * EB);
+            const U32x4 v = *src;
 #endif
-            } else
-                xr[r][kc] = make_uint4(0u, 0u, 0u, 0u);
+            xr[r][kc] = make_uint4(v.x, v.y, v.z, v.w);
         }
+    }
 
     // eta for the R rows of the tile, reduced across the wave.  While a lane
     // holds more than one row, each exchange step halves them: the lane's bit
