@@ -35,14 +35,13 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
                                                 uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t a = 0xD2511F53u * c0;
-        const uint32_t ah = __umulhi(0xD2511F53u, c0);
-        const uint32_t b = 0xCD9E8D57u * c2;
-        const uint32_t bh = __umulhi(0xCD9E8D57u, c2);
-        c0 = bh ^ c1 ^ k0;
-        c1 = b;
-        c2 = ah ^ c3 ^ k1;
-        c3 = a;
+        // each product whole, in one 32 x 32 -> 64-bit multiply
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+        c0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        c1 = (uint32_t)pb;
+        c2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c3 = (uint32_t)pa;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
