@@ -208,7 +208,7 @@ SweepArgs sweep_args(hsp_state* s, uint32_t mode) {
     a.mode = mode;
     a.timeout_ticks = s->timeout_ticks;
     a.trace = dev_ptr(s->trace);
-    a.gp = a.gz = a.zgroups = a.block0 = 0;
+    a.gp = a.gz = a.zgroups = a.block0 = a.idle = 0;
     const uint32_t nt = (s->x.p + kTile - 1) / kTile;
     a.subst = s->x.p > (uint32_t)kSmallP && !with_inverse(nt) ? 1u : 0u;
     return a;
@@ -770,6 +770,7 @@ hsp_status stream_args(hsp_state* s, uint32_t mode) {
         h.x.N = rows;
         h.first_row = r0;
         h.gp = 0;
+        h.idle = 0;
         const uint32_t tiles = (rows + s->plan.rows - 1) / s->plan.rows;
         h.gz = std::max<uint32_t>(1, std::min<uint32_t>(s->plan.gz, (tiles + 3) / 4));
         h.zgroups = (h.gz + kZGroup - 1) / kZGroup;

@@ -167,6 +167,7 @@ struct SweepArgs {
     uint32_t gz;             // z-pass blocks (after the group)
     uint32_t zgroups;        // ceil(gz / kZGroup)
     uint32_t block0;         // first grid block of this chain (several chains share a pack launch)
+    uint32_t idle;           // a grid block that leaves at once (0: none), see sweep_finish_args
     uint64_t timeout_ticks;  // bound of every wait, in s_memrealtime ticks
     HSP_GLOBAL uint64_t* trace;         // optional: kTraceSlots timestamps per group block
     HSP_GLOBAL const uint32_t* tasks;   // tile path: every group block's task list, concatenated
@@ -275,6 +276,7 @@ struct SweepPlan {
     int chunks;    // 16-byte vectors per lane per row
     int rows;      // rows per wave tile
     int capacity;  // resident blocks of the chosen kernel on the device
+    uint32_t cus = 0;  // compute units of the device
     uint32_t static_pct = kZStaticPctDefault;
     uint32_t unit = kZUnitDefault;
 };
