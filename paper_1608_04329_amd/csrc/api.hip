@@ -1595,6 +1595,14 @@ hsp_status batch_tune(hsp_batch* b) {
         if (m < b->chains.size()) pmaxs.push_back(m);
     double best_ms = 1e300;
     uint32_t best_mc = 0, best_bw = 100, best_pm = 0, best_zq = 0;
+    // every candidate is timed over a few replays; the best few are timed
+    // again over more (the least of many short, noisy timings favours
+    // whichever candidate was lucky)
+    struct Cand {
+        double ms;
+        uint32_t mc, bw, pm, zq;
+    };
+    std::vector<Cand> cands;
     auto trial = [&](uint32_t pm, uint32_t mc, uint32_t bw, uint32_t zq) -> hsp_status {
         b->mc_gz = mc;
         b->bw_pct = bw;
@@ -1605,6 +1613,7 @@ hsp_status batch_tune(hsp_batch* b) {
         if (!s2) s2 = time_batch(b, 1, 3, &ms);
         free_packs(b);
         if (s2) return s2;
+        cands.push_back(Cand{ms, mc, bw, pm, zq});
         if (ms < best_ms) {
             best_ms = ms;
             best_mc = mc;
@@ -1614,6 +1623,7 @@ hsp_status batch_tune(hsp_batch* b) {
         }
         return HSP_OK;
     };
+    constexpr int kLongWarm = 2, kLongTimed = 12;
     // a shared z queue per pack: its unit size, blocks per multi-chain pass
     // and chains per pack
     for (uint32_t zq : {32u, 64u, 128u})
@@ -1628,6 +1638,29 @@ hsp_status batch_tune(hsp_batch* b) {
         for (uint32_t pm : pmaxs)
             for (uint32_t bw : {60u, 100u, 160u})
                 if ((st = trial(pm, mc, bw, 0)) != HSP_OK) return st;
+    {
+        std::sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+        best_ms = 1e300;
+        for (size_t i = 0; i < cands.size() && i < 3; ++i) {
+            const Cand& c = cands[i];
+            b->mc_gz = c.mc;
+            b->bw_pct = c.bw;
+            b->pack_max = c.pm;
+            b->zq_kib = c.zq;
+            st = batch_build(b);
+            double ms = 0.0;
+            if (!st) st = time_batch(b, kLongWarm, kLongTimed, &ms);
+            free_packs(b);
+            if (st) return st;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_mc = c.mc;
+                best_bw = c.bw;
+                best_pm = c.pm;
+                best_zq = c.zq;
+            }
+        }
+    }
     b->mc_gz = best_mc;
     b->bw_pct = best_bw;
     b->pack_max = best_pm;
@@ -1641,7 +1674,7 @@ hsp_status batch_tune(hsp_batch* b) {
             b->pre_gp = pg;
             st = batch_build(b);
             double ms = 0.0;
-            if (!st) st = time_batch(b, 1, 3, &ms);
+            if (!st) st = time_batch(b, kLongWarm, kLongTimed, &ms);
             free_packs(b);
             if (st) return st;
             if (ms < best_ms) {
@@ -1657,7 +1690,7 @@ hsp_status batch_tune(hsp_batch* b) {
         b->overlap = false;
         st = batch_build(b);
         double ms = 0.0;
-        if (!st) st = time_batch(b, 1, 3, &ms);
+        if (!st) st = time_batch(b, kLongWarm, kLongTimed, &ms);
         free_packs(b);
         if (st) return st;
         if (ms < best_ms) {
