@@ -303,12 +303,13 @@ def run_large_p(a, N=1_000_000, p=10_000, sweeps=20):
     s.close()
     nbytes = N * p * 4 + N
     flops = p ** 3 / 3.0 + 2.0 * p * p + 4.0 * N * p
-    hbm = roofline(nbytes, kernel_ms, None)
+    workload = f"horseshoe_probit_gibbs_N{N}_p{p}_xf32"
+    hbm = roofline(nbytes, kernel_ms, stored_traffic(a.traffic_json, workload))
     fp64 = {"bound": "mfma", "achieved": round(flops / (kernel_ms * 1e-3) / 1e12, 2), "peak": 78.6,
             "unit": "TFLOP/s", "frac": round(flops / (kernel_ms * 1e-3) / 1e12 / 78.6, 4), "traffic": None,
             "flops_per_launch": flops, "flops_counted": "p^3/3 Cholesky + 2p^2 solves + 4Np for X beta and X^T z"}
     return {
-        "workload": f"horseshoe_probit_gibbs_N{N}_p{p}_xf32",
+        "workload": workload,
         "value": round(sweeps / elapsed, 3), "unit": "sweeps/s", "sweeps": sweeps,
         "ms_per_step": round(1e3 * elapsed / sweeps, 4), "kernel_ms": round(kernel_ms, 4),
         "launch_plan": {"group_blocks": plan[0], "z_blocks": plan[1], "chosen": plan[4]},
@@ -376,12 +377,13 @@ def run_rare(a, sweeps=10_000, burn=2_500):
     gauss = (att & (1 << 30)) != 0
     rho1, ess = ess_and_acf(betas[burn:])
     nbytes = d.N * d.p * 4 + d.N
+    workload = f"horseshoe_probit_rare_event_N{d.N}_p{d.p}_ybar{d.y.mean():.4f}_xf32"
     return {
-        "workload": f"horseshoe_probit_rare_event_N{d.N}_p{d.p}_ybar{d.y.mean():.4f}_xf32",
+        "workload": workload,
         "value": round(sweeps / elapsed, 2), "unit": "sweeps/s",
         "sweeps": sweeps, "burn_in": burn, "seconds_for_run": round(elapsed, 3),
         "kernel_ms": round(kernel_ms, 5),
-        "roofline": roofline(nbytes, kernel_ms, None),
+        "roofline": roofline(nbytes, kernel_ms, stored_traffic(a.traffic_json, workload)),
         "acf_lag1": {"min": round(float(rho1.min()), 4), "median": round(float(np.median(rho1)), 4),
                      "max": round(float(rho1.max()), 4), "intercept": round(float(rho1[0]), 4)},
         "ess": {"min": round(float(ess.min()), 1), "median": round(float(np.median(ess)), 1),
