@@ -239,8 +239,11 @@ const char* hsp_last_error(const hsp_state* s);
  * except chains that share a bfloat16 design under multi_chain_z: their
  * X beta and X^T z run as bfloat16 matrix-core products with beta and z
  * split into two bfloat16 parts each (error <= 2^-18 relative per term, then
- * float32 accumulation).  They follow the same conditionals and counters, are
- * bit-reproducible run to run, but round differently from a lone chain. */
+ * float32 accumulation), and for p > 16 their beta comes from blocked
+ * substitution through the Cholesky factor (their factorisation runs beside
+ * or after the pass, not under a pass of their own, and leaves L^-1 out).
+ * They follow the same conditionals and counters, are bit-reproducible run
+ * to run, but round differently from a lone chain. */
 typedef struct hsp_batch hsp_batch; /* opaque, owned by the library */
 
 typedef struct {

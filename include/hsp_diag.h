@@ -36,7 +36,9 @@ hsp_status hsp_get_phase_trace(hsp_state* s, uint64_t* out, int64_t* group_block
  * Cholesky factorisation of Q by 64 x 64 tiles (Section 5, beta step iii),
  * with the same row operations applied to an identity block, is split into
  * tile tasks that the p-side blocks of the sweep kernel run.  nt =
- * ceil(p / 64) tiles per side, gp blocks.
+ * ceil(p / 64) tiles per side, gp blocks; inverse: 1 with the L^-1 tasks,
+ * 0 without them (beta then by blocked substitution), -1 as a lone chain of
+ * that size has it (with them up to 24 tiles).
  * Task code: type (bits 0-1: 0 factor a diagonal tile, 1 triangular solve of
  * a tile of the block row, 2 tile update, 3 the next diagonal tile's solve,
  * update and factorisation in one block) | part (bit 2: 0 U, 1 L^-1) | step
@@ -46,10 +48,10 @@ hsp_status hsp_get_phase_trace(hsp_state* s, uint64_t* out, int64_t* group_block
  * queue that the other blocks claim tasks from, in order.  tasks (capacity
  * cap) receives the lists, off (3 entries) their bounds, *n_tasks the total
  * count (also when cap is too small, then HSP_ERANGE).  Errors: HSP_EINVAL
- * if nt < 1, nt > hsp_max_p() / 64 or gp < 1.  Test hook for the schedule's coverage and
- * deadlock freedom. */
-hsp_status hsp_tile_schedule(int64_t nt, int64_t gp, uint32_t* tasks, int64_t cap, uint32_t* off,
-                             int64_t* n_tasks);
+ * if nt < 1, nt > hsp_max_p() / 64, gp < 1 or inverse is not -1, 0 or 1.
+ * Test hook for the schedule's coverage and deadlock freedom. */
+hsp_status hsp_tile_schedule(int64_t nt, int64_t gp, int32_t inverse, uint32_t* tasks, int64_t cap,
+                             uint32_t* off, int64_t* n_tasks);
 
 /* Read ceiling of this GPU for the state's design: the mean milliseconds of
  * one pass of a plain streaming read (16-byte non-temporal loads, nothing

@@ -337,7 +337,7 @@ hsp_status chain_impl(hsp_state* s);
 hsp_status upload_schedule(hsp_state* s) {
     const uint32_t nt = (s->x.p + kTile - 1) / kTile;
     std::vector<uint32_t> tasks, off;
-    chol_schedule(nt, s->plan.gp, &tasks, &off);
+    chol_schedule(nt, s->plan.gp, &tasks, &off, with_inverse(nt));
     if (s->tasks) (void)hipFree(s->tasks);
     if (s->task_off) (void)hipFree(s->task_off);
     s->tasks = s->task_off = nullptr;
@@ -1340,10 +1340,16 @@ hsp_status plan_packs(hsp_batch* b) {
                 h.zq = dev_ptr(pk.dq);
             }
             h.block0 = blk;
+            // the chains of a multi-chain pass factor Q beside or after the
+            // pass, not under a pass of their own: there the factorisation
+            // without L^-1 (half the tile tasks and their traffic) and beta
+            // by substitution take less time than the inverse and the two
+            // products (they already round differently from a lone chain)
+            if ((pk.mc || pk.pre || pk.split) && s->x.p > (uint32_t)kSmallP) h.subst = 1u;
             if (s->x.p > (uint32_t)kSmallP && !pk.split) {
                 const uint32_t nt = (s->x.p + kTile - 1) / kTile;
                 std::vector<uint32_t> tasks, off;
-                chol_schedule(nt, h.gp, &tasks, &off);
+                chol_schedule(nt, h.gp, &tasks, &off, h.subst == 0u);
                 uint32_t *dt = nullptr, *doff = nullptr;
                 if (dalloc(&dt, tasks.size()) || dalloc(&doff, off.size()))
                     return batch_fail(b, HSP_ENOMEM, "pack allocation failed");
@@ -1515,7 +1521,7 @@ std::string batch_tune_key(const hsp_batch* b) {
     char hex[17];
     std::snprintf(hex, sizeof hex, "%016llx", (unsigned long long)h);
     const hsp_state* s0 = b->chains[0];
-    return "batch-v5 " + device_tag(s0->device, s0->num_cus) + " chains=" + std::to_string(b->chains.size()) +
+    return "batch-v6 " + device_tag(s0->device, s0->num_cus) + " chains=" + std::to_string(b->chains.size()) +
            " h=" + hex;
 }
 
@@ -2336,12 +2342,12 @@ hsp_status hsp_read_ceiling(hsp_state* s, int32_t iters, double* ms_per_pass, do
     return HSP_OK;
 }
 
-hsp_status hsp_tile_schedule(int64_t nt, int64_t gp, uint32_t* tasks, int64_t cap, uint32_t* off,
-                             int64_t* n_tasks) {
-    if (nt < 1 || nt > kMaxP / kTile || gp < 1 || gp > 4096 || !n_tasks)
+hsp_status hsp_tile_schedule(int64_t nt, int64_t gp, int32_t inverse, uint32_t* tasks, int64_t cap,
+                             uint32_t* off, int64_t* n_tasks) {
+    if (nt < 1 || nt > kMaxP / kTile || gp < 1 || gp > 4096 || inverse < -1 || inverse > 1 || !n_tasks)
         return fail(nullptr, HSP_EINVAL, "bad arguments");
     std::vector<uint32_t> t, o;
-    chol_schedule((uint32_t)nt, (uint32_t)gp, &t, &o);
+    chol_schedule((uint32_t)nt, (uint32_t)gp, &t, &o, inverse < 0 ? with_inverse((uint32_t)nt) : inverse != 0);
     *n_tasks = (int64_t)t.size();
     if ((int64_t)t.size() > cap || !tasks || !off)
         return fail(nullptr, HSP_ERANGE, "task buffer too small");

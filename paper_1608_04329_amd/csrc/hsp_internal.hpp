@@ -267,8 +267,11 @@ __host__ __device__ constexpr uint32_t task_code(uint32_t type, uint32_t part, u
 // 11.5 against 6.5 ms).
 constexpr int kSubstP = 1536;
 constexpr bool with_inverse(uint32_t nt) { return nt * (uint32_t)kTile <= (uint32_t)kSubstP; }
+// inverse: whether the L^-1 tasks are part of the graph (a lone chain:
+// with_inverse(nt); the chains of a multi-chain pass, whose factorisation
+// does not hide under a pass of their own, leave them out)
 void chol_schedule(uint32_t nt, uint32_t gp, std::vector<uint32_t>* tasks,
-                   std::vector<uint32_t>* off);
+                   std::vector<uint32_t>* off, bool inverse);
 
 struct SweepPlan {
     uint32_t gp;

@@ -50,11 +50,11 @@ struct Task {
 }  // namespace
 
 void chol_schedule(uint32_t nt, uint32_t gp, std::vector<uint32_t>* tasks,
-                   std::vector<uint32_t>* off) {
+                   std::vector<uint32_t>* off, bool inverse) {
     // rough costs in units of one tile task
     const double c_potrf = 3.5, c_panel = 4.5, c_trsm = 1.0, c_gemm = 1.0;
     const bool chain = gp > 1;  // block 0 owns the critical chain
-    const bool inv = with_inverse(nt);  // the L^-1 tasks (TRSM_L, GEMM_L) are part of the graph
+    const bool inv = inverse;  // the L^-1 tasks (TRSM_L, GEMM_L) are part of the graph
     std::vector<Task> t;
     auto idx3 = [nt](uint32_t k, uint32_t i, uint32_t j) { return ((size_t)k * nt + i) * nt + j; };
     // ids: potrf[k] (k = 0, or every k without a chain block), panel[k] (k >= 1 with one),

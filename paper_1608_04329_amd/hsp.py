@@ -93,7 +93,7 @@ def load():
     L.hsp_set_phase_trace.argtypes = [vp, i32]; L.hsp_set_phase_trace.restype = st
     L.hsp_get_phase_trace.argtypes = [vp, vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(d)]
     L.hsp_get_phase_trace.restype = st
-    L.hsp_tile_schedule.argtypes = [i64, i64, vp, i64, vp, C.POINTER(i64)]
+    L.hsp_tile_schedule.argtypes = [i64, i64, i32, vp, i64, vp, C.POINTER(i64)]
     L.hsp_tile_schedule.restype = st
     L.hsp_read_ceiling.argtypes = [vp, i32, C.POINTER(d), C.POINTER(d)]
     L.hsp_read_ceiling.restype = st
@@ -240,18 +240,20 @@ def hsp_philox(seed, ctr):
     return out
 
 
-def hsp_tile_schedule(nt, gp):
+def hsp_tile_schedule(nt, gp, inverse=None):
     """Task lists of the tiled factorisation: (tasks, list bounds).
 
     One list for a group of one block; otherwise block 0's chain list and the
-    shared queue of the other blocks."""
+    shared queue of the other blocks.  inverse: with the L^-1 tasks (True),
+    without (False), or as a lone chain of nt tiles has it (None)."""
+    inv = -1 if inverse is None else int(bool(inverse))
     n = C.c_int64()
-    st = load().hsp_tile_schedule(nt, gp, None, 0, None, C.byref(n))
+    st = load().hsp_tile_schedule(nt, gp, inv, None, 0, None, C.byref(n))
     if st not in (HSP_OK, HSP_ERANGE):
         _check(st)
     tasks = np.zeros(max(n.value, 1), np.uint32)
     off = np.zeros(3, np.uint32)
-    _check(load().hsp_tile_schedule(nt, gp, _hp(tasks), tasks.size, _hp(off), C.byref(n)))
+    _check(load().hsp_tile_schedule(nt, gp, inv, _hp(tasks), tasks.size, _hp(off), C.byref(n)))
     return tasks[: n.value], off[: 2 if gp == 1 else 3]
 
 

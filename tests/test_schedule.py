@@ -29,7 +29,7 @@ def with_inverse(nt):
     return nt * 64 <= 1536
 
 
-def expected_tasks(nt, chain):
+def expected_tasks(nt, chain, inv=None):
     """Right-looking blocked Cholesky of [Q | I]: every tile operation once.
 
     With a chain block, PANEL(k) (k >= 1) stands for the solve of tile
@@ -37,7 +37,7 @@ def expected_tasks(nt, chain):
     tile (k, k).  Without the inverse, the L^-1 tasks (part 1) are left out.
     """
     out = set()
-    inv = with_inverse(nt)
+    inv = with_inverse(nt) if inv is None else inv
     for k in range(nt):
         out.add((PANEL, 0, k, k, k) if chain and k > 0 else (POTRF, 0, k, k, k))
         out.update((TRSM, 0, k, k, j) for j in range(k + 1, nt) if not (chain and j == k + 1))
@@ -85,7 +85,7 @@ def write(t, vU, vL):
         vL[r, c] = k - j + 1
 
 
-def replay(chain_list, queue, nqb, nt, rng):
+def replay(chain_list, queue, nqb, nt, rng, inv=None):
     """Event simulation of the device: block 0 runs chain_list in order; nqb
     other blocks claim queue entries in order, each reserving its next entry
     when it starts a task (as the kernel does), and wait on tile versions."""
@@ -126,7 +126,7 @@ def replay(chain_list, queue, nqb, nt, rng):
         cur[b] = cur[b] + 1 if b == 0 else nxt[b]
         busy[b] = False
         left -= 1
-    inv = with_inverse(nt)
+    inv = with_inverse(nt) if inv is None else inv
     for i in range(nt):
         for j in range(nt):
             if i <= j:
@@ -136,8 +136,8 @@ def replay(chain_list, queue, nqb, nt, rng):
     return now
 
 
-def lists_of(nt, gp):
-    tasks, off = hsp.hsp_tile_schedule(nt, gp)
+def lists_of(nt, gp, inv=None):
+    tasks, off = hsp.hsp_tile_schedule(nt, gp, inv)
     dec = [decode(int(c)) for c in tasks]
     if gp == 1:
         assert len(off) == 2
@@ -146,20 +146,25 @@ def lists_of(nt, gp):
     return dec[off[0]:off[1]], dec[off[1]:off[2]], gp - 1
 
 
-@pytest.mark.parametrize("nt,gp", [(1, 1), (2, 1), (3, 2), (5, 32), (16, 32), (16, 7), (20, 32), (24, 48),
-                                   (25, 48), (40, 96), (70, 384)])
-def test_schedule_covers_every_task_and_never_deadlocks(nt, gp):
-    tasks, off = hsp.hsp_tile_schedule(nt, gp)
+@pytest.mark.parametrize("nt,gp,inv", [(1, 1, None), (2, 1, None), (3, 2, None), (5, 32, None), (16, 32, None),
+                                       (16, 7, None), (20, 32, None), (24, 48, None), (25, 48, None),
+                                       (40, 96, None), (70, 384, None),
+                                       # the chains of a multi-chain pass leave L^-1 out at any size
+                                       (1, 1, False), (3, 2, False), (16, 32, False), (16, 7, False),
+                                       # and a forced inverse beyond 24 tiles
+                                       (25, 48, True)])
+def test_schedule_covers_every_task_and_never_deadlocks(nt, gp, inv):
+    tasks, off = hsp.hsp_tile_schedule(nt, gp, inv)
     assert off[0] == 0 and off[-1] == len(tasks) and np.all(np.diff(off.astype(np.int64)) >= 0)
-    chain_list, queue, nqb = lists_of(nt, gp)
+    chain_list, queue, nqb = lists_of(nt, gp, inv)
     dec = chain_list + queue
     chain = gp > 1
-    assert len(dec) == len(set(dec)) and set(dec) == expected_tasks(nt, chain)
+    assert len(dec) == len(set(dec)) and set(dec) == expected_tasks(nt, chain, inv)
     if chain:  # block 0 runs the critical chain, in order, and nothing else
         assert chain_list == [(POTRF, 0, 0, 0, 0)] + [(PANEL, 0, k, k, k) for k in range(1, nt)]
     rng = np.random.default_rng(nt * 100 + gp)
     for _ in range(5 if nt < 16 else 2):
-        replay(chain_list, queue, nqb, nt, rng)
+        replay(chain_list, queue, nqb, nt, rng, inv)
 
 
 def test_schedule_shortens_with_more_blocks():
@@ -191,3 +196,7 @@ def test_schedule_rejects_bad_arguments():
         hsp.hsp_tile_schedule(hsp.hsp_max_p() // 64 + 1, 4)
     with pytest.raises(hsp.HspError):
         hsp.hsp_tile_schedule(4, 0)
+    with pytest.raises(hsp.HspError):
+        load_raw = hsp.load()
+        n = hsp.C.c_int64()
+        hsp._check(load_raw.hsp_tile_schedule(4, 2, 2, None, 0, None, hsp.C.byref(n)))
